@@ -1,0 +1,186 @@
+#!/usr/bin/env python3
+"""Benchmark of the fused DPF-PIR server path on one MI355X.
+
+One step = one pir_answer call: 512 key pairs (1024 keys, both servers' keys
+answered on this GPU) over one table of 2^20 rows x 64 uint32 (256 MiB, rows of
+2048 bits), uniform query indices, AES-128 PRF: the workload of the paper's
+PRF comparison (Table 5: 1,048,576 entries, batch 512, lambda = 128).
+
+Prints one JSON line.  `value` is server-QPS: keys answered per second by this
+GPU, the unit of the paper's per-GPU QPS.  Inputs are resident in HBM before
+the timed region; keys come from the library's own Gen.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from pathlib import Path
+
+import numpy as np
+
+ROOT = Path(__file__).resolve().parent
+sys.path.insert(0, str(ROOT))
+
+METRIC = "PIR queries/sec on 1 MI355X (exact) batched vs single-query; p50/p99 ms"
+PAPER_V100_QPS = 965.0  # Table 5, AES-128 row, same table shape and batch (context only)
+
+# Algorithmic int32 operations, T-table AES-128 formulation (4 tables):
+#   key expansion 10 rounds x (4 byte extracts + 4 lookups + 3 merges + 1 rcon + 4 xor) = 160
+#   one block: initial AddRoundKey 4 + 10 rounds x 16 x (extract + lookup + xor)   = 484
+#   one internal node: key expansion + 2 blocks + 2 x 4 codeword xors               = 1136
+#   contraction per leaf and key: dim x (multiply + add)
+OPS_PER_NODE = 160 + 2 * 484 + 8
+PEAK_INT32_OPS = 256 * 64 * 2.4e9  # CUs x lanes/clk x clock: 39.3 T int32 op/s
+
+
+def percentile(xs, p):
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), p))
+
+
+def cpu_baseline(keys_np, table_np, sample_keys: int, threads: int):
+    """The oracle (untuned) on a bounded sample of the same workload."""
+    import oracle
+
+    O = oracle.Oracle()
+    sub = keys_np[:sample_keys]
+    t0 = time.perf_counter()
+    O.answer_batch(sub, table_np, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": sample_keys / dt, "unit": "server queries/s", "cores": threads,
+            "kind": "oracle",
+            "sample": f"{sample_keys} keys of the same workload (2^20 rows x 64 uint32), "
+                      f"one key per thread, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--pairs", type=int, default=512)
+    ap.add_argument("--log-rows", type=int, default=20)
+    ap.add_argument("--dim", type=int, default=64)
+    ap.add_argument("--seed", type=int, default=2)
+    ap.add_argument("--single-steps", type=int, default=50)
+    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the server path runs on a single MI355X "
+              "(multi-GPU row sharding is a design note, not built); run with --gpus 1",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    pir.load()
+    dev = torch.device("cuda:0")
+    rows, dim, pairs = 1 << args.log_rows, args.dim, args.pairs
+    n = pir.log_domain(rows)
+    table = W.make_table(rows, dim, args.seed, device=dev)
+    alphas = W.uniform_indices(rows, pairs, args.seed)
+    K0, K1 = pir.gen_batch(n, alphas, W.key_seeds(pairs, args.seed))
+    keys_np = np.concatenate([K0, K1])
+    keys = torch.from_numpy(keys_np).to(dev)
+    B = keys.shape[0]
+    out = torch.empty((B, dim), dtype=torch.int32, device=dev)
+    torch.cuda.synchronize()
+
+    for _ in range(args.warmup):
+        pir.answer(keys, table, out)
+    torch.cuda.synchronize()
+
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record()
+        pir.answer(keys, table, out)
+        e1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    launch_ms = [e0.elapsed_time(e1) for e0, e1 in evs]
+    elapsed = t1 - t0
+    ms_per_step = 1e3 * elapsed / args.steps
+    value = B * args.steps / elapsed
+
+    # exactness of what was timed: every reconstruction equals T[alpha]
+    got = out.cpu().numpy().view(np.uint32)
+    want = W.table_rows_np(alphas, dim, args.seed)
+    recon_ok = bool(all((pir.reconstruct(got[p], got[pairs + p]) == want[p]).all()
+                        for p in range(pairs)))
+
+    # the unbatched single-query kernel on the same table
+    k1 = keys[:1].contiguous()
+    o1 = torch.empty((1, dim), dtype=torch.int32, device=dev)
+    for _ in range(3):
+        pir.answer(k1, table, o1)
+    torch.cuda.synchronize()
+    sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.single_steps)]
+    s0 = time.perf_counter()
+    for e0, e1 in sev:
+        e0.record()
+        pir.answer(k1, table, o1)
+        e1.record()
+    torch.cuda.synchronize()
+    s1 = time.perf_counter()
+    single_ms = [e0.elapsed_time(e1) for e0, e1 in sev]
+
+    nodes = B * (rows - 1)
+    ops = nodes * OPS_PER_NODE + B * rows * dim * 2
+    kern_s = float(np.mean(launch_ms)) / 1e3
+    achieved = ops / kern_s / 1e12
+    peak = PEAK_INT32_OPS / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+                "kernel": "k_pir_fused", "ops_per_launch": ops,
+                "avg_launch_ms": round(kern_s * 1e3, 4)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = max(1, min(16, os.cpu_count() or 1))
+        cpu = cpu_baseline(keys_np, table.cpu().numpy().view(np.uint32), args.cpu_sample, threads)
+
+    res = {
+        "metric": METRIC,
+        "value": round(value, 2),
+        "unit": "server queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": round(value / PAPER_V100_QPS, 2) if (rows, dim, pairs) == (1 << 20, 64, 512) else None,
+        "vs_baseline_ref": "paper Table 5 AES-128, NVIDIA V100: 965 QPS (context, another GPU)",
+        "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": f"one table 2^{args.log_rows} rows x {dim} uint32, {pairs} key pairs "
+                               f"= {B} keys per step (both servers), uniform alpha, AES-128 PRF",
+                   "rows": rows, "dim": dim, "keys_per_step": B, "log_domain": n},
+        "retrieval_qps": round(value / 2, 2),
+        "batched_latency_ms": {"p50": round(percentile(launch_ms, 50), 4),
+                               "p99": round(percentile(launch_ms, 99), 4)},
+        "single_query": {"qps": round(args.single_steps / (s1 - s0), 2),
+                         "p50_ms": round(percentile(single_ms, 50), 4),
+                         "p99_ms": round(percentile(single_ms, 99), 4)},
+        "exact": recon_ok,
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+    if not recon_ok:
+        sys.exit(1)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,139 @@
+/*
+ * pir.h -- C ABI of the MI355X two-server DPF-PIR library (libpir.so).
+ *
+ * The calls follow the problem statement of the paper's section 3.1
+ * ("Fundamentals of PIR and DPF"):
+ *   - the client runs Gen(1^lambda, alpha) -> (k_a, k_b)          : dpf_gen
+ *   - each server computes T x Eval(k, {0 .. L-1}) over its table   : pir_answer,
+ *     which fuses the full-domain evaluation of the node recurrence, Eq.
+ *     (p1)-(p3), with the share-vector x table product (sections 3.2.3
+ *     "memory-bounded tree traversal" and 3.2.4 "operator fusion")
+ *   - the client adds the two answers                                : pir_reconstruct
+ *
+ * Conventions
+ *   - Every call returns an int status (PIR_OK or a negative PIR_E* code) and
+ *     never throws or aborts across the ABI.
+ *   - Pointers named d_* are device (HBM) pointers on the current HIP device;
+ *     all others are host pointers.  The caller owns every buffer; the library
+ *     keeps no pointer after a call returns.
+ *   - Device calls are asynchronous and ordered on the caller's HIP stream
+ *     (`stream` is a hipStream_t passed as void*; NULL is the default stream).
+ *     Launch errors are returned as PIR_EHIP (pir_last_hip_error() gives the
+ *     hipError_t); faults inside a kernel surface at the caller's next
+ *     synchronisation of that stream.
+ *   - Arithmetic on shares and answers is in Z_{2^32} (uint32 wrap-around).
+ *
+ * DPF key layout (bytes; dpf_key_size(n) = 32 + 64 n):
+ *   [0] version = 1   [1] party b in {0,1}   [2] n = log2 of the domain
+ *   [3] PRF id, 0 = AES-128 in counter mode   [4..15] zero
+ *   [16..31] root seed P(0,0) of party b (16 bytes)
+ *   [32 + 64 (d-1) + 32 t + 16 c .. +15] codeword C_t[c, d], d = 1..n,
+ *                                        t, c in {0,1}
+ *   The codeword part, 64 n bytes, is the key size the paper prints in its
+ *   Table 4 (896 / 1280 / 1408 bytes for 2^14 / 2^20 / 2^22 entries).
+ *
+ * Evaluation (what pir_answer computes for each key; Eq. (p1)-(p3)):
+ *   P(0,0) = root;  P(d,j) = AES128_{P(d-1, j/2)}(BE128(j mod 2))
+ *                            XOR C_{t(P(d-1, j/2))}[j mod 2, d]
+ *   with t(s) = bit 0 of byte 0 of s; the share of row j is
+ *   (-1)^b * (bytes 0..3 of P(n,j) read little-endian) mod 2^32.
+ */
+#ifndef PIR_H
+#define PIR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* status codes */
+#define PIR_OK 0
+#define PIR_EINVAL (-1) /* a bad argument: null pointer, size or shape     */
+#define PIR_ENOMEM (-2) /* a size beyond what the library supports          */
+#define PIR_EHIP (-3)   /* a HIP runtime call or kernel launch failed       */
+#define PIR_EKEY (-4)   /* a device-resident key had a bad header           */
+
+#define PIR_KEY_VERSION 1
+#define PIR_MAX_LOG_DOMAIN 32 /* n <= 32: tables of at most 2^32 rows */
+#define PIR_MAX_DIM 256       /* uint32 columns per row (1 KiB rows)  */
+
+/* Size in bytes of one DPF key over a domain of 2^n indices: 32 + 64 n.
+ * Returns 0 for n outside [1, 32]. */
+size_t dpf_key_size(uint32_t n);
+
+/* Client side Gen (paper section 3.1; the construction the paper defers to
+ * its DPF reference is written out in the library's design notes).
+ *   n      log2 of the domain, 1..32
+ *   alpha  the secret index, alpha < 2^n
+ *   beta   the value at alpha: Eval(k0, j) + Eval(k1, j) = beta * [j == alpha]
+ *   seed16 16 bytes of randomness; the 3n+1 random 16-byte draws of Gen are
+ *          the AES-128-CTR keystream under this key from counter 0.  NULL
+ *          draws the seed from the operating system (getrandom).
+ *   key0, key1  caller-owned host buffers of dpf_key_size(n) bytes each.
+ * Returns PIR_EINVAL for null key buffers, n outside [1,32] or alpha >= 2^n,
+ * and PIR_EHIP if the operating system refuses randomness. */
+int dpf_gen(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16,
+            uint8_t *key0, uint8_t *key1);
+
+/* Server side answer for one table (paper section 3.1: T x Eval(k, {0..L-1});
+ * fused evaluation as in sections 3.2.3-3.2.4).
+ *   d_keys     n_keys keys, key q at d_keys + q * key_stride (16-byte aligned,
+ *              key_stride a multiple of 16 and >= dpf_key_size(n))
+ *   d_table    row-major uint32 [rows][dim], 4-byte aligned, resident in HBM
+ *   rows       L, 1 <= rows <= 2^32; the keys' domain is n = ceil(log2 rows)
+ *              (n = 1 when rows = 1) and every key header must carry that n
+ *   dim        D, 1 <= dim <= PIR_MAX_DIM
+ *   d_out      uint32 [n_keys][dim]; fully overwritten:
+ *              d_out[q][k] = sum_{j<rows} Eval(key_q, j) * T[j][k] mod 2^32
+ *   stream     hipStream_t (void*), NULL for the default stream
+ * Keys may be of either party and mixed in one call.  A key whose header is
+ * bad (version, party, n or PRF id) gets an all-zero output row and raises
+ * the flag read by pir_check_status().  n_keys = 0 is a no-op returning PIR_OK.
+ * Returns PIR_EINVAL on null pointers, bad sizes or misalignment (nothing is
+ * launched), PIR_EHIP if a launch fails. */
+int pir_answer(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride,
+               const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out,
+               void *stream);
+
+/* One table of a multi-table call. */
+typedef struct {
+    const uint32_t *d_table; /* row-major uint32 [rows][dim] in HBM */
+    uint64_t rows;           /* L_t >= 1 */
+    uint32_t dim;            /* D_t, 1..PIR_MAX_DIM */
+    uint32_t n_keys;         /* keys for this table (may be 0) */
+} pir_table_t;
+
+/* Server side answer for keys over several tables of different sizes in one
+ * stream-ordered call (a batch grouped by table).
+ *   tables     host array of n_tables descriptors
+ *   d_keys     all keys, grouped by table in the order of `tables`: the first
+ *              tables[0].n_keys keys query table 0, and so on; key stride and
+ *              alignment as for pir_answer; each table's keys carry that
+ *              table's n = ceil(log2 rows)
+ *   d_out      answers packed in key order: key i of table t occupies dim_t
+ *              words starting at sum over earlier keys of their dim
+ * Errors as for pir_answer; any bad descriptor rejects the whole call. */
+int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t *d_keys,
+                     uint32_t key_stride, uint32_t *d_out, void *stream);
+
+/* Client side reconstruction (paper section 3.1): out[k] = a0[k] + a1[k]
+ * mod 2^32 for k < dim; host buffers.  PIR_EINVAL on null pointers. */
+int pir_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim, uint32_t *out);
+
+/* After the caller has synchronised its answering streams: PIR_EKEY if any
+ * key seen since the previous call had a bad header (and clears the flag),
+ * else PIR_OK; PIR_EHIP if the flag cannot be read. */
+int pir_check_status(void);
+
+/* Static, NUL-terminated description of a status code. */
+const char *pir_strerror(int status);
+
+/* The hipError_t of the last failed HIP call in this thread (0 if none). */
+int pir_last_hip_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

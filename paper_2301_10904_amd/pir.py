@@ -1,0 +1,221 @@
+"""Python binding of libpir.so (include/pir.h): argument marshalling only.
+
+Every step of the server path runs in the library's HIP kernels; PyTorch
+tensors only supply device memory (``data_ptr()``) and the HIP stream
+(``torch.cuda.current_stream().cuda_stream``).  There is no fallback: if the
+library is missing, ``load()`` raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from pathlib import Path
+
+import numpy as np
+
+PKG = Path(__file__).resolve().parent
+LIB_PATH = PKG / "libpir.so"
+
+PIR_OK, PIR_EINVAL, PIR_ENOMEM, PIR_EHIP, PIR_EKEY = 0, -1, -2, -3, -4
+MAX_DIM = 256
+
+# the exported C ABI, as declared in include/pir.h
+EXPORTS = ("dpf_key_size", "dpf_gen", "pir_answer", "pir_answer_multi", "pir_reconstruct",
+           "pir_check_status", "pir_strerror", "pir_last_hip_error")
+
+_lib = None
+
+
+class PirError(RuntimeError):
+    def __init__(self, status: int, what: str):
+        self.status = status
+        msg = _lib.pir_strerror(status).decode() if _lib is not None else str(status)
+        super().__init__(f"{what}: {msg} (status {status})")
+
+
+class PirTable(ctypes.Structure):
+    _fields_ = [("d_table", ctypes.c_void_p), ("rows", ctypes.c_uint64),
+                ("dim", ctypes.c_uint32), ("n_keys", ctypes.c_uint32)]
+
+
+def load(path: Path | None = None):
+    """Load libpir.so (built by paper_2301_10904_amd.build); raise if absent."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = Path(path) if path else LIB_PATH
+    if not p.exists():
+        raise ImportError(f"{p} is missing: build it with `python -m paper_2301_10904_amd.build` "
+                          "(there is no fallback path)")
+    lib = ctypes.CDLL(str(p))
+    u8p = ctypes.POINTER(ctypes.c_uint8)
+    u32p = ctypes.POINTER(ctypes.c_uint32)
+    lib.dpf_key_size.restype = ctypes.c_size_t
+    lib.dpf_key_size.argtypes = [ctypes.c_uint32]
+    lib.dpf_gen.restype = ctypes.c_int
+    lib.dpf_gen.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, u8p, u8p, u8p]
+    lib.pir_answer.restype = ctypes.c_int
+    lib.pir_answer.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                               ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.pir_answer_multi.restype = ctypes.c_int
+    lib.pir_answer_multi.argtypes = [ctypes.POINTER(PirTable), ctypes.c_uint32, ctypes.c_void_p,
+                                     ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.pir_reconstruct.restype = ctypes.c_int
+    lib.pir_reconstruct.argtypes = [u32p, u32p, ctypes.c_uint32, u32p]
+    lib.pir_check_status.restype = ctypes.c_int
+    lib.pir_check_status.argtypes = []
+    lib.pir_strerror.restype = ctypes.c_char_p
+    lib.pir_strerror.argtypes = [ctypes.c_int]
+    lib.pir_last_hip_error.restype = ctypes.c_int
+    lib.pir_last_hip_error.argtypes = []
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(status: int, what: str):
+    if status != PIR_OK:
+        raise PirError(status, what)
+
+
+def _u8(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _u32(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))
+
+
+def key_size(n: int) -> int:
+    return int(load().dpf_key_size(n))
+
+
+def log_domain(rows: int) -> int:
+    """n = ceil(log2 rows), at least 1: the key domain for a table of `rows` rows."""
+    return max(1, (int(rows) - 1).bit_length())
+
+
+def gen(n: int, alpha: int, beta: int = 1, seed: bytes | None = None):
+    """Client Gen: returns (key0, key1) as uint8 numpy arrays of key_size(n) bytes."""
+    lib = load()
+    ks = key_size(n)
+    if ks == 0:
+        raise PirError(PIR_EINVAL, "dpf_gen")
+    k0 = np.zeros(ks, np.uint8)
+    k1 = np.zeros(ks, np.uint8)
+    sd = None
+    if seed is not None:
+        sd = np.frombuffer(bytes(seed), np.uint8).copy()
+        if sd.size != 16:
+            raise ValueError("seed must be 16 bytes")
+    _check(lib.dpf_gen(n, alpha, beta & 0xFFFFFFFF, _u8(sd) if sd is not None else None,
+                       _u8(k0), _u8(k1)), "dpf_gen")
+    return k0, k1
+
+
+def gen_batch(n: int, alphas, seeds=None, beta: int = 1):
+    """Keys for a batch of indices: (keys0, keys1), each uint8 [B, key_size(n)]."""
+    B = len(alphas)
+    ks = key_size(n)
+    K0 = np.zeros((B, ks), np.uint8)
+    K1 = np.zeros((B, ks), np.uint8)
+    for q in range(B):
+        K0[q], K1[q] = gen(n, int(alphas[q]), beta, None if seeds is None else seeds[q])
+    return K0, K1
+
+
+def _stream_handle(stream):
+    import torch
+
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _check_dev(t, name, dtypes):
+    import torch
+
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a device tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} has dtype {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+
+
+def answer(keys, table, out=None, stream=None):
+    """Server answer for one table: out[q] = sum_j Eval(keys[q], j) * table[j] mod 2^32.
+
+    keys  : uint8 device tensor [B, stride] (stride a multiple of 16)
+    table : int32/uint32 device tensor [rows, dim]
+    out   : int32/uint32 device tensor [B, dim] (allocated if None)
+    """
+    import torch
+
+    lib = load()
+    _check_dev(keys, "keys", (torch.uint8,))
+    _check_dev(table, "table", (torch.int32, torch.uint32))
+    B, stride = keys.shape
+    rows, dim = table.shape
+    if out is None:
+        out = torch.empty((B, dim), dtype=torch.int32, device=table.device)
+    _check_dev(out, "out", (torch.int32, torch.uint32))
+    if tuple(out.shape) != (B, dim):
+        raise ValueError("out must be [B, dim]")
+    _check(lib.pir_answer(keys.data_ptr(), B, stride, table.data_ptr(), rows, dim, out.data_ptr(),
+                          _stream_handle(stream)), "pir_answer")
+    return out
+
+
+def answer_multi(tables, key_counts, keys, out=None, stream=None):
+    """Server answer over several tables in one call.
+
+    tables     : list of int32/uint32 device tensors [rows_t, dim_t]
+    key_counts : keys per table; keys are grouped by table in this order
+    keys       : uint8 device tensor [sum(key_counts), stride]
+    out        : flat int32 device tensor of sum_t key_counts[t] * dim_t words
+    Returns out and the list of per-table [n_t, dim_t] views into it.
+    """
+    import torch
+
+    lib = load()
+    _check_dev(keys, "keys", (torch.uint8,))
+    if len(tables) != len(key_counts):
+        raise ValueError("one key count per table")
+    descs = (PirTable * max(1, len(tables)))()
+    total = 0
+    for i, (t, c) in enumerate(zip(tables, key_counts)):
+        _check_dev(t, f"tables[{i}]", (torch.int32, torch.uint32))
+        descs[i] = PirTable(t.data_ptr(), t.shape[0], t.shape[1], int(c))
+        total += int(c) * t.shape[1]
+    if keys.shape[0] != sum(int(c) for c in key_counts):
+        raise ValueError("keys must hold sum(key_counts) rows")
+    if out is None:
+        out = torch.empty(total, dtype=torch.int32, device=keys.device)
+    _check_dev(out, "out", (torch.int32, torch.uint32))
+    if out.numel() != total:
+        raise ValueError("out has the wrong size")
+    _check(lib.pir_answer_multi(descs, len(tables), keys.data_ptr(), keys.shape[1], out.data_ptr(),
+                                _stream_handle(stream)), "pir_answer_multi")
+    views, off = [], 0
+    for t, c in zip(tables, key_counts):
+        n = int(c) * t.shape[1]
+        views.append(out[off:off + n].view(int(c), t.shape[1]))
+        off += n
+    return out, views
+
+
+def reconstruct(a0: np.ndarray, a1: np.ndarray) -> np.ndarray:
+    """Client reconstruction a0 + a1 mod 2^32 (host arrays)."""
+    lib = load()
+    a0 = np.ascontiguousarray(a0).view(np.uint32).reshape(-1)
+    a1 = np.ascontiguousarray(a1).view(np.uint32).reshape(-1)
+    if a0.size != a1.size:
+        raise ValueError("answers differ in length")
+    out = np.zeros_like(a0)
+    _check(lib.pir_reconstruct(_u32(a0), _u32(a1), a0.size, _u32(out)), "pir_reconstruct")
+    return out
+
+
+def check_status() -> int:
+    """PIR_OK, or PIR_EKEY if a key with a bad header was seen (clears the flag)."""
+    return int(load().pir_check_status())

@@ -1,0 +1,203 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle.
+
+Keys always come from the oracle's Gen, tables from the seeded generator, and
+expected values from the oracle (or from the closed form beta * T[alpha]); no
+input or expected value is taken from the HIP path.  The bar is bit-exact:
+every comparison below is on uint32 words.
+"""
+import numpy as np
+import pytest
+
+from conftest import cpu_threads
+from paper_2301_10904_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_keys(O, n, alphas, seed):
+    seeds = W.key_seeds(len(alphas), seed)
+    return O.gen_batch(n, alphas, seeds)
+
+
+def gpu_answer(pir, keys_np, table_dev):
+    import torch
+
+    keys = torch.from_numpy(np.ascontiguousarray(keys_np)).cuda()
+    out = pir.answer(keys, table_dev)
+    torch.cuda.synchronize()
+    return out.cpu().numpy().view(np.uint32)
+
+
+def log_domain(rows):
+    return max(1, (rows - 1).bit_length())
+
+
+@pytest.fixture(scope="module")
+def pirmod(gpu_lib):
+    from paper_2301_10904_amd import pir
+
+    return pir
+
+
+def test_single_pair_2p14_x16(O, pirmod):
+    """One table of 2^14 rows x 16 uint32, one key pair over a 14-bit domain,
+    beta = 1: both per-server answers bit-exact and the reconstruction."""
+    import torch
+
+    rows, dim, seed = 1 << 14, 16, 1
+    T = W.make_table(rows, dim, seed)
+    alpha = W.uniform_indices(rows, 1, seed)
+    K0, K1 = oracle_keys(O, 14, alpha, seed)
+    keys = np.concatenate([K0, K1])
+    got = gpu_answer(pirmod, keys, T.cuda())
+    Tn = T.numpy().view(np.uint32)
+    want = O.answer_batch(keys, Tn, nthreads=2)
+    assert (got == want).all()
+    assert (O.reconstruct(got[0], got[1]) == Tn[alpha[0]]).all()
+    torch.cuda.synchronize()
+
+
+SHAPES = [
+    # rows, dim, key pairs: empty-ish, ragged tails, several tiles, wide rows
+    (1, 1, 1), (2, 3, 1), (3, 5, 2), (5, 1, 3), (100, 7, 2), (1000, 16, 9),
+    (4097, 64, 8), (5000, 65, 3), (3000, 130, 5), (2048, 256, 10), (1 << 16, 32, 20),
+    (50000, 64, 1), (1 << 15, 64, 40),
+]
+
+
+@pytest.mark.parametrize("rows,dim,pairs", SHAPES)
+def test_parity_shapes(O, pirmod, rows, dim, pairs):
+    seed = rows * 7 + dim
+    n = log_domain(rows)
+    T = W.make_table(rows, dim, seed)
+    alphas = W.uniform_indices(rows, pairs, seed)
+    alphas[0] = rows - 1  # the last row is always queried
+    K0, K1 = oracle_keys(O, n, alphas, seed)
+    # both parties mixed in one call, interleaved
+    keys = np.empty((2 * pairs, K0.shape[1]), np.uint8)
+    keys[0::2], keys[1::2] = K0, K1
+    got = gpu_answer(pirmod, keys, T.cuda())
+    Tn = T.numpy().view(np.uint32)
+    want = O.answer_batch(keys, Tn, nthreads=cpu_threads())
+    assert (got == want).all()
+    for p in range(pairs):
+        assert (O.reconstruct(got[2 * p], got[2 * p + 1]) == Tn[alphas[p]]).all()
+
+
+def test_beta_values(O, pirmod):
+    rows, dim = 3000, 8
+    T = W.make_table(rows, dim, 5)
+    Tn = T.numpy().view(np.uint32).astype(np.uint64)
+    keys, expect = [], []
+    for i, beta in enumerate((0, 2, 2**31, 2**32 - 1, 0x12345678)):
+        seed = W.key_seeds(1, 100 + i)[0].tobytes()
+        k0, k1 = O.gen(12, 17 * i, beta, seed)
+        keys += [k0, k1]
+        expect.append(((Tn[17 * i] * beta) & 0xFFFFFFFF).astype(np.uint32))
+    keys = np.stack(keys)
+    got = gpu_answer(pirmod, keys, T.cuda())
+    want = O.answer_batch(keys, T.numpy().view(np.uint32), nthreads=cpu_threads())
+    assert (got == want).all()
+    for i, e in enumerate(expect):
+        assert (O.reconstruct(got[2 * i], got[2 * i + 1]) == e).all()
+
+
+def test_full_size_2p20_x64_batch512(O, pirmod):
+    """The benchmark's workload and launch: 2^20 rows x 64 uint32 (256 MiB),
+    512 key pairs (1024 keys, both servers in one call).  Every reconstruction
+    must equal T[alpha]; per-server answers are compared with the oracle on a
+    sample of keys."""
+    import torch
+
+    rows, dim, pairs, seed = 1 << 20, 64, 512, 2
+    T = W.make_table(rows, dim, seed, device="cuda")
+    alphas = W.uniform_indices(rows, pairs, seed)
+    K0, K1 = oracle_keys(O, 20, alphas, seed)
+    keys = np.concatenate([K0, K1])
+    got = gpu_answer(pirmod, keys, T)
+    Trows = W.table_rows_np(alphas, dim, seed)
+    for p in range(pairs):
+        assert (O.reconstruct(got[p], got[pairs + p]) == Trows[p]).all(), p
+    # the device table is the generator's table
+    Tn = T.cpu().numpy().view(np.uint32)
+    assert (Tn[alphas[:16]] == Trows[:16]).all()
+    sample = np.array([0, 1, 255, 511, 512, 700, 1022, 1023])
+    want = O.answer_batch(keys[sample], Tn, nthreads=cpu_threads())
+    assert (got[sample] == want).all()
+    del T
+    torch.cuda.empty_cache()
+
+
+def test_bad_key_header_gives_zero_row(O, pirmod):
+    rows, dim = 1024, 16
+    T = W.make_table(rows, dim, 9)
+    K0, K1 = oracle_keys(O, 10, np.array([3, 600]), 9)
+    keys = np.concatenate([K0, K1])
+    keys[1, 0] = 7          # bad version
+    keys[2, 2] = 11         # wrong domain size
+    assert pirmod.check_status() == pirmod.PIR_OK
+    got = gpu_answer(pirmod, keys, T.cuda())
+    assert pirmod.check_status() == pirmod.PIR_EKEY
+    assert pirmod.check_status() == pirmod.PIR_OK  # flag cleared
+    assert (got[1] == 0).all() and (got[2] == 0).all()
+    want = O.answer_batch(keys[[0, 3]], T.numpy().view(np.uint32), nthreads=2)
+    assert (got[[0, 3]] == want).all()
+
+
+def test_repeat_launches_identical(O, pirmod):
+    import torch
+
+    rows, dim = 1 << 14, 64
+    T = W.make_table(rows, dim, 4).cuda()
+    K0, K1 = oracle_keys(O, 14, W.uniform_indices(rows, 24, 4), 4)
+    keys = torch.from_numpy(np.concatenate([K0, K1])).cuda()
+    first = pirmod.answer(keys, T).clone()
+    for _ in range(5):
+        out = pirmod.answer(keys, T)
+        torch.cuda.synchronize()
+        assert torch.equal(out, first)
+
+
+def test_side_stream(O, pirmod):
+    import torch
+
+    rows, dim = 3000, 32
+    T = W.make_table(rows, dim, 6)
+    K0, K1 = oracle_keys(O, 12, W.uniform_indices(rows, 3, 6), 6)
+    keys_np = np.concatenate([K0, K1])
+    s = torch.cuda.Stream()
+    Td = T.cuda()
+    keys = torch.from_numpy(keys_np).cuda()
+    torch.cuda.synchronize()
+    with torch.cuda.stream(s):
+        out = pirmod.answer(keys, Td, stream=s)
+    s.synchronize()
+    want = O.answer_batch(keys_np, T.numpy().view(np.uint32), nthreads=cpu_threads())
+    assert (out.cpu().numpy().view(np.uint32) == want).all()
+
+
+def test_answer_multi_ragged(O, pirmod):
+    import torch
+
+    specs = [(1 << 12, 32, 5), (3000, 16, 0), (1 << 14, 64, 7), (777, 8, 2)]
+    tables, counts, all_keys, expect = [], [], [], []
+    for i, (rows, dim, pairs) in enumerate(specs):
+        T = W.make_table(rows, dim, 40 + i)
+        tables.append(T.cuda())
+        counts.append(2 * pairs)
+        if pairs == 0:
+            expect.append(None)
+            continue
+        K0, K1 = oracle_keys(O, log_domain(rows), W.zipf_indices(rows, pairs, 40 + i), 40 + i)
+        keys = np.concatenate([K0, K1])
+        all_keys.append(keys)
+        expect.append(O.answer_batch(keys, T.numpy().view(np.uint32), nthreads=cpu_threads()))
+    stride = max(k.shape[1] for k in all_keys)
+    stride = (stride + 15) // 16 * 16
+    padded = [np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in all_keys]
+    keys_dev = torch.from_numpy(np.concatenate(padded)).cuda()
+    _, views = pirmod.answer_multi(tables, counts, keys_dev)
+    torch.cuda.synchronize()
+    for v, e in zip(views, expect):
+        if e is not None:
+            assert (v.cpu().numpy().view(np.uint32) == e).all()

@@ -1,0 +1,117 @@
+"""Host-side checks of libpir.so that need no GPU.
+
+  - the library loads and exports every function include/pir.h declares;
+  - the library's Gen (its own AES and code) and the oracle's Gen produce
+    byte-identical keys from the same 16-byte seed;
+  - argument validation returns PIR_EINVAL before anything is launched;
+  - reconstruction and status strings.
+"""
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_2301_10904_amd import pir
+
+ROOT = Path(__file__).resolve().parent.parent
+
+
+def declared_functions():
+    text = (ROOT / "include" / "pir.h").read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^[A-Za-z_][\w \*]*?\b([a-z_][a-z0-9_]*)\s*\(", text, flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    return pir.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert set(names) == set(pir.EXPORTS), names
+    for name in names:
+        assert hasattr(lib, name), name
+
+
+def test_key_size(lib):
+    assert pir.key_size(1) == 96
+    assert pir.key_size(20) == 32 + 1280
+    assert lib.dpf_key_size(0) == 0 and lib.dpf_key_size(33) == 0
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 8, 14, 20, 25, 32])
+def test_gen_matches_oracle_bytes(O, n):
+    rng = np.random.default_rng(n)
+    for trial in range(4):
+        alpha = int(rng.integers(0, 1 << n))
+        beta = int(rng.integers(0, 2**32)) if trial else 1
+        seed = rng.integers(0, 256, 16, dtype=np.uint8).tobytes()
+        k0, k1 = pir.gen(n, alpha, beta, seed)
+        o0, o1 = O.gen(n, alpha, beta, seed)
+        assert (k0 == o0).all() and (k1 == o1).all(), (n, alpha, beta)
+
+
+def test_gen_without_seed_is_random_and_correct(O):
+    k0, k1 = pir.gen(6, 17)
+    k0b, _ = pir.gen(6, 17)
+    assert not (k0[16:] == k0b[16:]).all()
+    s = (O.eval_full(k0) + O.eval_full(k1)).astype(np.uint32)
+    want = np.zeros(64, np.uint32)
+    want[17] = 1
+    assert (s == want).all()
+
+
+def test_gen_rejects_bad_arguments():
+    for n, alpha in ((0, 0), (33, 0), (4, 16), (1, 2)):
+        with pytest.raises(pir.PirError) as e:
+            pir.gen(n, alpha, 1, bytes(16))
+        assert e.value.status == pir.PIR_EINVAL
+
+
+def test_reconstruct_wraps():
+    a0 = np.array([1, 2**32 - 1, 5], np.uint32)
+    a1 = np.array([2**32 - 1, 2, 7], np.uint32)
+    assert (pir.reconstruct(a0, a1) == np.array([0, 1, 12], np.uint32)).all()
+
+
+def test_strerror(lib):
+    for st in (0, -1, -2, -3, -4, 99):
+        assert isinstance(lib.pir_strerror(st), bytes)
+    assert lib.pir_strerror(pir.PIR_EKEY) != lib.pir_strerror(pir.PIR_OK)
+
+
+def test_answer_validation_without_gpu(lib):
+    """Every rejected call returns before touching the HIP runtime."""
+    fake = ctypes.c_void_p(0x1000)  # never dereferenced: validation fails first
+    ks = pir.key_size(10)
+    cases = [
+        (None, 1, ks, fake, 1024, 4, fake),        # null keys
+        (fake, 1, ks, None, 1024, 4, fake),        # null table
+        (fake, 1, ks, fake, 1024, 4, None),        # null out
+        (fake, 1, ks, fake, 0, 4, fake),           # no rows
+        (fake, 1, ks, fake, 1024, 0, fake),        # no columns
+        (fake, 1, ks, fake, 1024, 257, fake),      # too many columns
+        (fake, 1, ks, fake, 2**32 + 1, 4, fake),   # rows beyond 2^32
+        (fake, 1, ks - 16, fake, 1024, 4, fake),   # stride below the key size
+        (fake, 1, ks + 8, fake, 1024, 4, fake),    # stride not a multiple of 16
+        (ctypes.c_void_p(0x1008), 1, ks, fake, 1024, 4, fake),  # misaligned keys
+    ]
+    for c in cases:
+        assert lib.pir_answer(*c, None) == pir.PIR_EINVAL, c
+    # zero keys is a no-op
+    assert lib.pir_answer(None, 0, ks, None, 1024, 4, None, None) == pir.PIR_OK
+
+
+def test_answer_multi_validation_without_gpu(lib):
+    fake = 0x1000
+    ks = pir.key_size(12)
+    T = (pir.PirTable * 2)(pir.PirTable(fake, 4096, 8, 3), pir.PirTable(fake, 0, 8, 2))
+    assert lib.pir_answer_multi(T, 2, fake, ks, fake, None) == pir.PIR_EINVAL
+    T = (pir.PirTable * 1)(pir.PirTable(fake, 4096, 300, 3))
+    assert lib.pir_answer_multi(T, 1, fake, ks, fake, None) == pir.PIR_EINVAL
+    T = (pir.PirTable * 1)(pir.PirTable(fake, 4096, 8, 0))
+    assert lib.pir_answer_multi(T, 1, None, ks, None, None) == pir.PIR_OK
