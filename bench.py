@@ -27,13 +27,88 @@ sys.path.insert(0, str(ROOT))
 METRIC = "PIR queries/sec on 1 MI355X (exact) batched vs single-query; p50/p99 ms"
 PAPER_V100_QPS = 965.0  # Table 5, AES-128 row, same table shape and batch (context only)
 
-# Algorithmic int32 operations, T-table AES-128 formulation (4 tables):
-#   key expansion 10 rounds x (4 byte extracts + 4 lookups + 3 merges + 1 rcon + 4 xor) = 160
-#   one block: initial AddRoundKey 4 + 10 rounds x 16 x (extract + lookup + xor)   = 484
-#   one internal node: key expansion + 2 blocks + 2 x 4 codeword xors               = 1136
-#   contraction per leaf and key: dim x (multiply + add)
-OPS_PER_NODE = 160 + 2 * 484 + 8
-PEAK_INT32_OPS = 256 * 64 * 2.4e9  # CUs x lanes/clk x clock: 39.3 T int32 op/s
+# Algorithmic work of the fused kernel, per internal node of the DPF tree
+# (AES-128 key expansion + two counter blocks, T-table formulation with one
+# v_perm per table address, three-input XORs and the TE/TE8 table pair):
+#   key expansion, per round: 4 addresses + 2 byte selects + 1 xor3 + 1 rcon + 3 xor = 11
+#   round-key rotations for rounds 1..9: 4 per round
+#   middle round, per column: 4 addresses + 2 xor3 + 1 rotation = 7
+#   last round, per column: 4 addresses + 2 byte selects + 1 xor3 = 7
+#   block 1 shares 3 of the 4 columns of round 1 with block 0
+#   full node  : 110 + 36 + 9*28 + (9*28 - 21) + 2*28 + 8 codeword xors + 1 = 694 VALU ops
+#   bottom node (children are leaves, only bytes 0..3 needed):
+#                107 + 36 + 252 + 231 + 2*7 + 2 + 1                          = 643 VALU ops
+#   LDS table lookups: full node 40 + 160 + 148 = 348, bottom node 348 - 24 = 324
+#   contraction: dim x (multiply + add) VALU ops per leaf and key.
+VALU_FULL_NODE, VALU_BOTTOM_NODE = 694, 643
+LOOKUPS_FULL_NODE, LOOKUPS_BOTTOM_NODE = 348, 324
+PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x VALU lanes per clock x clock: 39.3 T int32 op/s
+PEAK_LDS_LOOKUPS = 256 * 32 * 2.4e9  # CUs x 128 B/clk of LDS reads / 4 B: 19.7 T lookups/s
+KERNEL_SOURCES = ["paper_2301_10904_amd/csrc/pir_device.hip", "paper_2301_10904_amd/csrc/aes_gfx950.h",
+                  "paper_2301_10904_amd/csrc/aes_tables.h"]
+TRAFFIC_SUMMARY = ROOT / "profiles" / "k_pir_fused_2p20x64_b1024_traffic.json"
+
+
+def algorithmic_work(n: int, keys: int, dim: int):
+    """(VALU ops, LDS lookups) of one launch over a full 2^n-leaf domain."""
+    leaves = 1 << n
+    bottom = leaves // 2
+    full = bottom - 1
+    valu = keys * (full * VALU_FULL_NODE + bottom * VALU_BOTTOM_NODE + leaves * 2 * dim)
+    lds = keys * (full * LOOKUPS_FULL_NODE + bottom * LOOKUPS_BOTTOM_NODE)
+    return valu, lds
+
+
+def kernel_digest() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        h.update((ROOT / f).read_bytes())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per launch from the committed PMC summary, if the kernel is unchanged."""
+    try:
+        t = json.loads(TRAFFIC_SUMMARY.read_text())
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_digest") != kernel_digest():
+        return None
+    return t.get("bytes_per_launch")
+
+
+def pmc_summary(paths, kernel_substr="k_pir_", copy_mib=256):
+    """Summarise rocprofv3 --pmc CSVs: per-dispatch counter values of the fused
+    kernel, and FETCH/WRITE scale factors from the plain copy of copy_mib MiB."""
+    import csv
+    import collections
+
+    per = collections.defaultdict(dict)
+    copy = collections.defaultdict(list)
+    for p in paths:
+        for r in csv.DictReader(open(p)):
+            name, cn, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
+            if kernel_substr in name and "<1," not in name:
+                per[(p, r["Dispatch_Id"])][cn] = per[(p, r["Dispatch_Id"])].get(cn, 0.0) + v
+            elif "copyBuffer" in name:
+                copy[(p, r["Dispatch_Id"], cn)].append(v)
+    counters = collections.defaultdict(list)
+    for d in per.values():
+        for cn, v in d.items():
+            counters[cn].append(v)
+    avg = {cn: sum(v) / len(v) for cn, v in counters.items()}
+    big_copy = {}
+    for (p, did, cn), vs in copy.items():
+        tot = sum(vs)
+        big_copy.setdefault(cn, []).append(tot)
+    scale = {}
+    for cn in ("FETCH_SIZE", "WRITE_SIZE"):
+        if cn in big_copy:
+            kib = max(big_copy[cn])  # the calibration copy is the largest copy dispatch
+            scale[cn] = copy_mib * 1024 / kib
+    return avg, scale, len(per)
 
 
 def percentile(xs, p):
@@ -67,7 +142,22 @@ def main():
     ap.add_argument("--single-steps", type=int, default=50)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
+                    help="summarise rocprofv3 --pmc counter CSVs of this benchmark and exit")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="also run a plain device copy of MIB MiB (read + write) three times, "
+                         "to scale HBM traffic counters")
     args = ap.parse_args()
+
+    if args.pmc_summary:
+        avg, scale, dispatches = pmc_summary(args.pmc_summary, copy_mib=args.calibrate_copy or 256)
+        out = {"kernel": "batched fused kernel (the 1024-key launch)", "dispatches": dispatches, "counters_avg": avg,
+               "copy_scale": scale, "kernel_digest": kernel_digest()}
+        if "FETCH_SIZE" in avg and "WRITE_SIZE" in avg and len(scale) == 2:
+            out["bytes_per_launch"] = int(1024 * (avg["FETCH_SIZE"] * scale["FETCH_SIZE"] +
+                                                  avg["WRITE_SIZE"] * scale["WRITE_SIZE"]))
+        print(json.dumps(out, indent=1))
+        return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the server path runs on a single MI355X "
@@ -135,15 +225,27 @@ def main():
     s1 = time.perf_counter()
     single_ms = [e0.elapsed_time(e1) for e0, e1 in sev]
 
-    nodes = B * (rows - 1)
-    ops = nodes * OPS_PER_NODE + B * rows * dim * 2
+    if args.calibrate_copy:
+        src = torch.empty(args.calibrate_copy << 18, dtype=torch.int32, device=dev).fill_(1)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+
+    valu_ops, lookups = algorithmic_work(n, B, dim)
     kern_s = float(np.mean(launch_ms)) / 1e3
-    achieved = ops / kern_s / 1e12
+    achieved = valu_ops / kern_s / 1e12
     peak = PEAK_INT32_OPS / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-                "kernel": "k_pir_fused", "ops_per_launch": ops,
-                "avg_launch_ms": round(kern_s * 1e3, 4)}
+                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
+                "kernel": "k_pir_fused", "valu_ops_per_launch": valu_ops,
+                "avg_launch_ms": round(kern_s * 1e3, 4), "kernel_digest": kernel_digest()}
+    lds_rate = lookups / kern_s / 1e12
+    roofline_lds = {"achieved": round(lds_rate, 3), "peak": round(PEAK_LDS_LOOKUPS / 1e12, 3),
+                    "unit": "T lookups/s", "frac": round(lds_rate * 1e12 / PEAK_LDS_LOOKUPS, 4),
+                    "lookups_per_launch": lookups}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -175,6 +277,7 @@ def main():
                          "p99_ms": round(percentile(single_ms, 99), 4)},
         "exact": recon_ok,
         "roofline": roofline,
+        "roofline_lds": roofline_lds,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

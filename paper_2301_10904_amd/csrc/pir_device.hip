@@ -11,7 +11,7 @@
 // per level, and the product fused at the leaves; here it is re-planned for
 // 64-wide wavefronts and a large LDS):
 //   * A work item is (group of Q keys, chunk of 2^H rows).  One workgroup of
-//     256 lanes owns an item: S = 256/Q lanes per key.
+//     512 lanes owns an item: S = 512/Q lanes per key.
 //   * Descent: Q lanes walk from each root to the chunk's subtree root.
 //   * Breadth-first expansion in LDS until every lane holds one node.
 //   * Each lane then walks its own subtree of height h depth-first with the
@@ -24,24 +24,26 @@
 //     atomics into out; integer addition mod 2^32 makes the result exact and
 //     independent of the order.
 //
-// AES-128 runs on little-endian column words with the combined
-// SubBytes/MixColumns table TE replicated 32 times across the LDS banks, so
-// lane l always reads bank (l mod 32) and table lookups never conflict.
+// AES-128 (aes_gfx950.h) runs on little-endian column words with the combined
+// SubBytes/MixColumns tables replicated per lane in LDS, so table lookups never
+// conflict; the tables fill the first 64 KiB, and two workgroups share a CU.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 
+#include "aes_gfx950.h"
 #include "aes_tables.h"
 #include "pir.h"
 #include "pir_internal.h"
 
 namespace {
 
-constexpr int NT = 256;            // lanes per workgroup
-constexpr int NW = NT / 64;        // waves per workgroup
-constexpr int HMAX = 10;           // largest per-lane subtree height
-constexpr int TAB_REPL = 32;       // TE copies, one per LDS bank
-constexpr int TAB_WORDS = 256 * TAB_REPL;
+using namespace pir_dev;
+
+constexpr int NT = 512;      // lanes per workgroup
+constexpr int NW = NT / 64;  // waves per workgroup
+constexpr int HMAX = 10;     // largest per-lane subtree height
+constexpr int QMAX = 16;     // keys per workgroup
 
 __constant__ pir_aes::Words256 c_TE = pir_aes::TE;
 __device__ uint32_t g_key_error;
@@ -50,112 +52,15 @@ struct Seed {
     uint32_t w[4];
 };
 
-struct Tab {
-    const uint32_t *lds;
-    uint32_t lane;
-    __device__ __forceinline__ uint32_t te(uint32_t x) const { return lds[(x << 5) | lane]; }
+// The whole LDS of a workgroup.
+struct Smem {
+    uint32_t tab[AES_TAB_WORDS];   // 64 KiB, later reused for the cross-wave sums
+    union {
+        Seed bfs[NT];              // breadth-first nodes
+        uint32_t sh[2 * NT];       // leaf shares of one walk step: [2 S][Q]
+    } u;
+    uint32_t keyok[QMAX];          // 0 = skip, 1 = party 0, 2 = party 1
 };
-
-__device__ __forceinline__ uint32_t b0(uint32_t w) { return w & 0xff; }
-__device__ __forceinline__ uint32_t b1(uint32_t w) { return (w >> 8) & 0xff; }
-__device__ __forceinline__ uint32_t b2(uint32_t w) { return (w >> 16) & 0xff; }
-__device__ __forceinline__ uint32_t b3(uint32_t w) { return w >> 24; }
-__device__ __forceinline__ uint32_t rotl(uint32_t x, int k) { return (x << k) | (x >> (32 - k)); }
-
-// SubWord(RotWord(w)) ^ rcon, little-endian words; S(x) is byte 1 of TE(x)
-__device__ __forceinline__ uint32_t ks_word(const Tab &T, uint32_t w, uint32_t rcon)
-{
-    uint32_t t0 = T.te(b1(w)), t1 = T.te(b2(w)), t2 = T.te(b3(w)), t3 = T.te(b0(w));
-    return (((t0 >> 8) & 0xffu) | (t1 & 0xff00u) | ((t2 << 8) & 0xff0000u) |
-            ((t3 << 16) & 0xff000000u)) ^
-           rcon;
-}
-
-__device__ __forceinline__ void next_round_key(const Tab &T, uint32_t k[4], uint32_t rcon)
-{
-    k[0] ^= ks_word(T, k[3], rcon);
-    k[1] ^= k[0];
-    k[2] ^= k[1];
-    k[3] ^= k[2];
-}
-
-__device__ __forceinline__ uint32_t mix_col(const Tab &T, uint32_t a, uint32_t b, uint32_t c,
-                                            uint32_t d, uint32_t k)
-{
-    return T.te(b0(a)) ^ rotl(T.te(b1(b)), 8) ^ rotl(T.te(b2(c)), 16) ^ rotl(T.te(b3(d)), 24) ^ k;
-}
-
-__device__ __forceinline__ uint32_t last_col(const Tab &T, uint32_t a, uint32_t b, uint32_t c,
-                                             uint32_t d, uint32_t k)
-{
-    uint32_t ta = T.te(b0(a)), tb = T.te(b1(b)), tc = T.te(b2(c)), td = T.te(b3(d));
-    return (((ta >> 8) & 0xffu) | (tb & 0xff00u) | (tc & 0xff0000u) | ((td << 16) & 0xff000000u)) ^ k;
-}
-
-__device__ __forceinline__ void full_round(const Tab &T, uint32_t s[4], const uint32_t k[4])
-{
-    uint32_t t0 = mix_col(T, s[0], s[1], s[2], s[3], k[0]);
-    uint32_t t1 = mix_col(T, s[1], s[2], s[3], s[0], k[1]);
-    uint32_t t2 = mix_col(T, s[2], s[3], s[0], s[1], k[2]);
-    uint32_t t3 = mix_col(T, s[3], s[0], s[1], s[2], k[3]);
-    s[0] = t0;
-    s[1] = t1;
-    s[2] = t2;
-    s[3] = t3;
-}
-
-__device__ __forceinline__ void final_round(const Tab &T, uint32_t s[4], const uint32_t k[4])
-{
-    uint32_t t0 = last_col(T, s[0], s[1], s[2], s[3], k[0]);
-    uint32_t t1 = last_col(T, s[1], s[2], s[3], s[0], k[1]);
-    uint32_t t2 = last_col(T, s[2], s[3], s[0], s[1], k[2]);
-    uint32_t t3 = last_col(T, s[3], s[0], s[1], s[2], k[3]);
-    s[0] = t0;
-    s[1] = t1;
-    s[2] = t2;
-    s[3] = t3;
-}
-
-// PRF_s(0) and PRF_s(1): AES-128 under key s of the counter blocks 0 and 1.
-// The key schedule runs once, interleaved with the two encryptions.
-__device__ __forceinline__ void prf_pair(const Tab &T, const Seed &s, uint32_t a[4], uint32_t b[4])
-{
-    uint32_t k[4] = {s.w[0], s.w[1], s.w[2], s.w[3]};
-    a[0] = k[0];
-    a[1] = k[1];
-    a[2] = k[2];
-    a[3] = k[3];
-    b[0] = k[0];
-    b[1] = k[1];
-    b[2] = k[2];
-    b[3] = k[3] ^ 0x01000000u; // counter 1 = byte 15
-#pragma unroll
-    for (int r = 1; r <= 9; r++) {
-        next_round_key(T, k, pir_aes::RCON.v[r]);
-        full_round(T, a, k);
-        full_round(T, b, k);
-    }
-    next_round_key(T, k, pir_aes::RCON.v[10]);
-    final_round(T, a, k);
-    final_round(T, b, k);
-}
-
-// Only the first output word (bytes 0..3) of both blocks: all a leaf needs.
-__device__ __forceinline__ void prf_pair_low32(const Tab &T, const Seed &s, uint32_t &y0, uint32_t &y1)
-{
-    uint32_t k[4] = {s.w[0], s.w[1], s.w[2], s.w[3]};
-    uint32_t a[4] = {k[0], k[1], k[2], k[3]};
-    uint32_t b[4] = {k[0], k[1], k[2], k[3] ^ 0x01000000u};
-#pragma unroll
-    for (int r = 1; r <= 9; r++) {
-        next_round_key(T, k, pir_aes::RCON.v[r]);
-        full_round(T, a, k);
-        full_round(T, b, k);
-    }
-    next_round_key(T, k, pir_aes::RCON.v[10]);
-    y0 = last_col(T, a[0], a[1], a[2], a[3], k[0]);
-    y1 = last_col(T, b[0], b[1], b[2], b[3], k[0]);
-}
 
 struct KeyView {
     const uint8_t *p; // key base (16-byte aligned)
@@ -171,20 +76,21 @@ struct KeyView {
         c0 = q[0];
         c1 = q[1];
     }
-    __device__ __forceinline__ uint32_t cw_low32(uint32_t d, uint32_t t, uint32_t c) const
+    __device__ __forceinline__ uint2 cw_word0(uint32_t d, uint32_t t) const
     {
-        return *reinterpret_cast<const uint32_t *>(p + 32 + 64 * (size_t)(d - 1) + 32 * t + 16 * c);
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(p + 32 + 64 * (size_t)(d - 1) + 32 * t);
+        return make_uint2(q[0], q[4]);
     }
 };
 
-// Both children of the node with seed s at depth d - 1 (codeword level d).
-__device__ __forceinline__ void children(const Tab &T, const KeyView &K, const Seed &s, uint32_t d,
-                                         Seed &c0, Seed &c1)
+// Both children of the node with seed s, codeword level d (Eq. (p3)).
+__device__ __forceinline__ void children(const Lanes &L, const KeyView &K, const Seed &s, uint32_t d, Seed &c0,
+                                         Seed &c1)
 {
     uint4 w0, w1;
     K.cw(d, s.w[0] & 1u, w0, w1);
     uint32_t a[4], b[4];
-    prf_pair(T, s, a, b);
+    prf_pair(s.w, a, b, L);
     c0 = Seed{{a[0] ^ w0.x, a[1] ^ w0.y, a[2] ^ w0.z, a[3] ^ w0.w}};
     c1 = Seed{{b[0] ^ w1.x, b[1] ^ w1.y, b[2] ^ w1.z, b[3] ^ w1.w}};
 }
@@ -205,7 +111,7 @@ struct Geometry {
     uint32_t n_chunks; // row chunks
 };
 
-// Q keys per group; KCH column chunks of 64 (dim <= 64 KCH).
+// Q keys per group (Q <= QMAX); KCH column chunks of 64 (dim <= 64 KCH).
 template <int Q, int KCH>
 __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ keys, uint32_t n_keys,
                                                   uint32_t stride, const uint32_t *__restrict__ table,
@@ -213,83 +119,78 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
                                                   Geometry g)
 {
     constexpr int S = NT / Q;
-    __shared__ uint32_t s_tab[TAB_WORDS];
-    __shared__ Seed s_bfs[2][NT];
-    __shared__ uint32_t s_sh[2 * S][Q];
-    __shared__ uint32_t s_keyok[Q];
+    __shared__ Smem sm;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63, wave = tid >> 6;
     const uint32_t grp = blockIdx.x % g.n_groups;
     const uint32_t chunk = blockIdx.x / g.n_groups;
     const uint64_t row_base = (uint64_t)chunk << g.H;
+    const Lanes L(sm.tab, lane);
 
-    for (uint32_t i = tid; i < TAB_WORDS; i += NT)
-        s_tab[i] = c_TE.v[i / TAB_REPL];
-    const Tab T{s_tab, lane & 31};
+    fill_tables(sm.tab, c_TE.v, tid, NT);
 
-    // key header check and the descent to the chunk's subtree root
+    // key headers; roots of the keys
     const uint32_t dtop = g.n - g.H;
     if (tid < Q) {
-        uint32_t kq = grp * Q + tid;
-        Seed s{{0, 0, 0, 0}};
+        const uint32_t kq = grp * Q + tid;
         uint32_t ok = 0;
+        Seed s{{0, 0, 0, 0}};
         if (kq < n_keys) {
-            KeyView K{keys + (size_t)kq * stride};
-            uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
-            uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
+            const KeyView K{keys + (size_t)kq * stride};
+            const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
+            const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
             ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == 0) ? 1u + party : 0u;
             if (!ok)
                 atomicOr(&g_key_error, 1u);
+            else
+                s = K.root();
         }
-        s_keyok[tid] = ok; // 0 = skip, 1 = party 0, 2 = party 1
-        if (ok) {
-            KeyView K{keys + (size_t)kq * stride};
-            s = K.root();
-            // the descent needs T, which every lane of this wave is still filling
-        }
-        s_bfs[0][tid] = s;
+        sm.keyok[tid] = ok;
+        sm.u.bfs[tid] = s;
     }
-    __syncthreads();
-    if (tid < Q && s_keyok[tid]) {
-        KeyView K{keys + (size_t)(grp * Q + tid) * stride};
-        Seed s = s_bfs[0][tid];
+    __syncthreads(); // tables and roots are in place
+
+    // descent from each root to the chunk's subtree root at depth n - H
+    if (tid < Q && sm.keyok[tid]) {
+        const KeyView K{keys + (size_t)(grp * Q + tid) * stride};
+        Seed s = sm.u.bfs[tid];
         for (uint32_t d = 1; d <= dtop; d++) {
             Seed c0, c1;
-            children(T, K, s, d, c0, c1);
+            children(L, K, s, d, c0, c1);
             s = ((row_base >> (g.n - d)) & 1) ? c1 : c0;
         }
-        s_bfs[0][tid] = s;
+        sm.u.bfs[tid] = s;
     }
     __syncthreads();
 
-    // breadth-first expansion in LDS: Q * 2^lgS nodes at depth dtop + lgS
-    int cur = 0;
+    // breadth-first expansion in LDS, in place: Q * 2^lgS nodes at depth dtop + lgS
     for (uint32_t l = 1; l <= g.lgS; l++) {
-        uint32_t half = 1u << (l - 1);
-        if (tid < Q * half) {
-            uint32_t q = tid >> (l - 1), j = tid & (half - 1);
-            if (s_keyok[q]) {
-                KeyView K{keys + (size_t)(grp * Q + q) * stride};
-                Seed c0, c1;
-                children(T, K, s_bfs[cur][tid], dtop + l, c0, c1);
-                s_bfs[cur ^ 1][q * 2 * half + 2 * j] = c0;
-                s_bfs[cur ^ 1][q * 2 * half + 2 * j + 1] = c1;
-            }
+        const uint32_t half = 1u << (l - 1);
+        const bool mine = tid < Q * half;
+        const uint32_t q = tid >> (l - 1), j = tid & (half - 1);
+        Seed c0{{0, 0, 0, 0}}, c1{{0, 0, 0, 0}};
+        if (mine && sm.keyok[q]) {
+            const KeyView K{keys + (size_t)(grp * Q + q) * stride};
+            children(L, K, sm.u.bfs[tid], dtop + l, c0, c1);
+        }
+        __syncthreads(); // every parent has been read
+        if (mine) {
+            sm.u.bfs[q * 2 * half + 2 * j] = c0;
+            sm.u.bfs[q * 2 * half + 2 * j + 1] = c1;
         }
         __syncthreads();
-        cur ^= 1;
     }
 
     // per-lane depth-first walk of a subtree of height h
     const uint32_t q = tid / S, ln = tid % S;
     const uint32_t S_used = 1u << g.lgS;
-    const bool active = ln < S_used && s_keyok[q];
-    const uint32_t h = g.H - g.lgS;            // >= 1
-    const uint32_t d0 = g.n - h;               // depth of the lane's root
-    const uint32_t steps = 1u << (h - 1);      // bottom nodes per lane
-    const KeyView K{keys + (size_t)(grp * Q + (q < Q ? q : 0)) * stride};
-    Seed node = active ? s_bfs[cur][q * S_used + ln] : Seed{{0, 0, 0, 0}};
+    const bool active = ln < S_used && sm.keyok[q];
+    const uint32_t h = g.H - g.lgS;       // >= 1
+    const uint32_t d0 = g.n - h;          // depth of the lane's root
+    const uint32_t steps = 1u << (h - 1); // bottom nodes per lane
+    const KeyView K{keys + (size_t)(grp * Q + q) * stride};
+    Seed node = active ? sm.u.bfs[q * S_used + ln] : Seed{{0, 0, 0, 0}};
     const Seed root = node;
     Seed right[HMAX];
 #pragma unroll
@@ -303,57 +204,56 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         for (int c = 0; c < KCH; c++)
             acc[i][c] = 0;
 
+    uint32_t(*sh)[Q] = reinterpret_cast<uint32_t(*)[Q]>(sm.u.sh);
     for (uint32_t m = 0; m < steps; m++) {
         uint32_t kst;
         if (m == 0) {
             node = root;
             kst = 1;
         } else {
-            uint32_t kf = h - 1 - __builtin_ctz(m);
+            const uint32_t kf = h - 1 - __builtin_ctz(m);
 #pragma unroll
             for (int i = 1; i < HMAX; i++)
                 if ((uint32_t)i == kf)
                     node = right[i];
             kst = kf + 1;
         }
+        uint32_t y0 = 0, y1 = 0;
         if (active) {
             for (uint32_t k = kst; k < h; k++) {
                 Seed c0, c1;
-                children(T, K, node, d0 + k, c0, c1);
+                children(L, K, node, d0 + k, c0, c1);
 #pragma unroll
                 for (int i = 1; i < HMAX; i++)
                     if ((uint32_t)i == k)
                         right[i] = c1;
                 node = c0;
             }
+            const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
+            prf_pair_word0(node.w, y0, y1, L);
+            y0 ^= cw.x;
+            y1 ^= cw.y;
         }
-        uint32_t y0 = 0, y1 = 0;
-        if (active) {
-            uint32_t t = node.w[0] & 1u;
-            prf_pair_low32(T, node, y0, y1);
-            y0 ^= K.cw_low32(g.n, t, 0);
-            y1 ^= K.cw_low32(g.n, t, 1);
-        }
-        __syncthreads(); // the previous step's readers are done with s_sh
+        __syncthreads(); // the previous step's readers are done with sh (and the roots were read)
         if (ln < S_used) {
-            s_sh[2 * ln][q] = y0;
-            s_sh[2 * ln + 1][q] = y1;
+            sh[2 * ln][q] = y0;
+            sh[2 * ln + 1][q] = y1;
         }
         __syncthreads();
         for (uint32_t i = wave; i < 2 * S_used; i += NW) {
-            uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
+            const uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
             if (row >= rows)
                 continue;
             const uint32_t *trow = table + row * dim;
             uint32_t tv[KCH];
 #pragma unroll
             for (int c = 0; c < KCH; c++) {
-                uint32_t col = lane + 64 * c;
+                const uint32_t col = lane + 64 * c;
                 tv[c] = col < dim ? trow[col] : 0u;
             }
 #pragma unroll
             for (int qq = 0; qq < Q; qq++) {
-                uint32_t y = s_sh[i][qq];
+                const uint32_t y = sh[i][qq];
 #pragma unroll
                 for (int c = 0; c < KCH; c++)
                     acc[qq][c] += y * tv[c];
@@ -361,9 +261,9 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         }
     }
 
-    // reduce the waves' partial sums in LDS (the table copy is no longer needed)
+    // reduce the waves' partial sums in LDS (the tables are no longer needed)
     __syncthreads();
-    uint32_t *s_acc = s_tab;
+    uint32_t *s_acc = sm.tab;
     for (uint32_t i = tid; i < Q * dim; i += NT)
         s_acc[i] = 0;
     __syncthreads();
@@ -371,20 +271,233 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     for (int qq = 0; qq < Q; qq++)
 #pragma unroll
         for (int c = 0; c < KCH; c++) {
-            uint32_t col = lane + 64 * c;
+            const uint32_t col = lane + 64 * c;
             if (col < dim)
                 atomicAdd(&s_acc[qq * dim + col], acc[qq][c]);
         }
     __syncthreads();
     for (uint32_t i = tid; i < Q * dim; i += NT) {
-        uint32_t qq = i / dim, col = i % dim;
-        uint32_t ok = s_keyok[qq];
+        const uint32_t qq = i / dim, col = i % dim;
+        const uint32_t ok = sm.keyok[qq];
         if (!ok)
             continue;
         uint32_t v = s_acc[i];
         if (ok == 2)
             v = 0u - v; // party 1 holds the negated share
         atomicAdd(&out[(size_t)(grp * Q + qq) * dim + col], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernel: every wave is an independent work item, and the share x
+// table product runs on the int8 matrix cores.
+//
+// A wave item is (16 keys, chunk of 4 * 2^h rows).  Lane l evaluates key
+// (l mod 16) over subtree (l / 16) of the chunk: it walks from the key's root
+// to the subtree root itself (n - h nodes, so no lane waits for another), then
+// depth-first over the subtree with the path in registers.  Each walk step
+// gives a lane the shares of two consecutive rows, so the 64 lanes together
+// hold an [16 keys x 8 rows] share tile, exactly the A operand layout of
+// v_mfma_i32_16x16x32_i8 (lane l: row l mod 16, K slice (l / 16) * 8 .. +7).
+//
+// Exactness mod 2^32 on int8 units: a uint32 x has balanced base-256 digits
+// d_0..d_3 in [-128, 127] with x = sum d_a 256^a (mod 2^32); they are the bytes
+// of (x + 0x80808080) ^ 0x80808080.  Then
+//     y * T = sum_{s=0..3} 256^s * sum_{a+b=s} d_a(y) e_b(T)      (mod 2^32),
+// so for each s one MFMA with A = digits of y arranged d_s, d_{s-1}, .., d_0
+// and B = digits of T gives the s-th term; the int32 accumulators wrap mod 2^32
+// and the four are combined with shifts at the end.
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int NW3 = 8;             // waves per workgroup (two workgroups per CU)
+constexpr int HMAX3 = 9;           // largest per-lane subtree height of the wave kernel
+constexpr int NT3 = 64 * NW3;
+
+struct Geo3 {
+    uint32_t n;        // log2 of the key domain
+    uint32_t h;        // per-lane subtree height (chunk = 4 * 2^h rows)
+    uint32_t n_groups; // key groups of 16
+    uint32_t n_items;  // n_groups * chunks
+};
+
+__device__ __forceinline__ uint32_t balanced(uint32_t x) { return (x + 0x80808080u) ^ 0x80808080u; }
+
+// digits of x arranged for shift s: byte j holds d_{s-j} (0 where j > s)
+template <int S>
+__device__ __forceinline__ uint32_t arrange(uint32_t x)
+{
+    if (S == 0)
+        return x & 0xffu;
+    constexpr uint32_t sel = S == 1 ? 0x0c0c0001u : S == 2 ? 0x0c000102u : 0x00010203u;
+    return __builtin_amdgcn_perm(x, x, sel);
+}
+
+__device__ __forceinline__ long pack2(uint32_t lo, uint32_t hi) { return (long)(((uint64_t)hi << 32) | lo); }
+
+// KT consecutive words T[r][c0 .. c0 + KT - 1] (zero outside the table).
+// VEC: dim == 16 KT, so the words are in bounds and 4 KT-byte aligned.
+template <int KT, bool VEC>
+__device__ __forceinline__ void load_cols(const uint32_t *__restrict__ table, uint64_t r, uint64_t rows, uint32_t dim,
+                                          uint32_t c0, uint32_t (&v)[KT])
+{
+    const bool row_ok = r < rows;
+    const uint32_t *p = table + (row_ok ? r : rows - 1) * dim;
+    if (VEC) {
+        if (KT == 4) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(p + c0);
+            v[0] = x.x;
+            v[KT > 1 ? 1 : 0] = x.y;
+            v[KT > 2 ? 2 : 0] = x.z;
+            v[KT > 3 ? 3 : 0] = x.w;
+        } else if (KT == 2) {
+            const uint2 x = *reinterpret_cast<const uint2 *>(p + c0);
+            v[0] = x.x;
+            v[KT > 1 ? 1 : 0] = x.y;
+        } else {
+            v[0] = p[c0];
+        }
+#pragma unroll
+        for (int t = 0; t < KT; t++)
+            v[t] = row_ok ? v[t] : 0u;
+    } else {
+#pragma unroll
+        for (int t = 0; t < KT; t++) {
+            const uint32_t c = c0 + t;
+            const uint32_t x = p[c < dim ? c : dim - 1];
+            v[t] = (row_ok && c < dim) ? x : 0u;
+        }
+    }
+}
+
+template <int KT, bool VEC>
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_waves(const uint8_t *__restrict__ keys, uint32_t n_keys,
+                                                   uint32_t stride, const uint32_t *__restrict__ table,
+                                                   uint64_t rows, uint32_t dim, uint32_t *__restrict__ out, Geo3 g)
+{
+    __shared__ uint32_t tab[AES_TAB_WORDS];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const Lanes L(tab, lane);
+    fill_tables(tab, c_TE.v, tid, NT3);
+    __syncthreads();
+
+    const uint32_t item = blockIdx.x * NW3 + wave;
+    if (item >= g.n_items)
+        return; // whole wave; no barrier follows
+    const uint32_t grp = item % g.n_groups, chunk = item / g.n_groups;
+    const uint32_t q = lane & 15, sub = lane >> 4;
+    const uint32_t kq = grp * 16 + q;
+    const uint32_t h = g.h;
+
+    uint32_t ok = 0;
+    const KeyView K{keys + (size_t)(kq < n_keys ? kq : 0) * stride};
+    if (kq < n_keys) {
+        const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
+        const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
+        ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == 0) ? 1u + party : 0u;
+        if (!ok && sub == 0)
+            atomicOr(&g_key_error, 1u);
+    }
+    const uint64_t lane_row0 = ((uint64_t)chunk * 4 + sub) << h;
+    const bool active = ok && lane_row0 < rows;
+
+    // walk from the root to this lane's subtree root (depth n - h)
+    Seed node{{0, 0, 0, 0}};
+    if (active) {
+        node = K.root();
+        for (uint32_t d = 1; d + h <= g.n; d++) {
+            Seed c0, c1;
+            children(L, K, node, d, c0, c1);
+            node = ((lane_row0 >> (g.n - d)) & 1) ? c1 : c0;
+        }
+    }
+    const uint32_t d0 = g.n - h;
+    Seed right[HMAX3];
+#pragma unroll
+    for (int i = 0; i < HMAX3; i++)
+        right[i] = Seed{{0, 0, 0, 0}};
+
+    // running sum over steps of sum_s 256^s D_s, per tile (wraps mod 2^32)
+    v4i tot[KT];
+#pragma unroll
+    for (int t = 0; t < KT; t++)
+        tot[t] = v4i{0, 0, 0, 0};
+
+    // this lane's table columns: tile t, column n = lane mod 16 -> n * KT + t
+    const uint32_t col0 = (lane & 15) * KT;
+    const uint32_t steps = 1u << (h - 1);
+    for (uint32_t m = 0; m < steps; m++) {
+        // table words of the two rows this lane feeds to the product; issued
+        // first and unconditionally (clamped addresses, masked values), so
+        // their latency hides behind this step's AES work
+        const uint64_t r0 = lane_row0 + 2 * m;
+        uint32_t t0[KT], t1[KT];
+        load_cols<KT, VEC>(table, r0, rows, dim, col0, t0);
+        load_cols<KT, VEC>(table, r0 + 1, rows, dim, col0, t1);
+
+        uint32_t kst = 1; // step 0 starts at the lane's root, already in `node`
+        if (m != 0) {
+            const uint32_t kf = h - 1 - __builtin_ctz(m);
+#pragma unroll
+            for (int i = 1; i < HMAX3; i++)
+                if ((uint32_t)i == kf)
+                    node = right[i];
+            kst = kf + 1;
+        }
+        uint32_t y0 = 0, y1 = 0;
+        if (active) {
+            for (uint32_t k = kst; k < h; k++) {
+                Seed c0, c1;
+                children(L, K, node, d0 + k, c0, c1);
+#pragma unroll
+                for (int i = 1; i < HMAX3; i++)
+                    if ((uint32_t)i == k)
+                        right[i] = c1;
+                node = c0;
+            }
+            const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
+            prf_pair_word0(node.w, y0, y1, L);
+            y0 ^= cw.x;
+            y1 ^= cw.y;
+        }
+
+        const uint32_t e0 = balanced(y0), e1 = balanced(y1);
+        const long a0 = pack2(arrange<0>(e0), arrange<0>(e1));
+        const long a1 = pack2(arrange<1>(e0), arrange<1>(e1));
+        const long a2 = pack2(arrange<2>(e0), arrange<2>(e1));
+        const long a3 = pack2(arrange<3>(e0), arrange<3>(e1));
+        const v4i zero = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < KT; t++) {
+            const long b = pack2(balanced(t0[t]), balanced(t1[t]));
+            const v4i c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b, zero, 0, 0, 0);
+            const v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b, zero, 0, 0, 0);
+            const v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a2, b, zero, 0, 0, 0);
+            const v4i c3 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3, b, zero, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+                tot[t][i] = (int)((uint32_t)tot[t][i] + (uint32_t)c0[i] + ((uint32_t)c1[i] << 8) +
+                                  ((uint32_t)c2[i] << 16) + ((uint32_t)c3[i] << 24));
+        }
+    }
+
+    // lane l holds D[(l / 16) * 4 + i][l mod 16] of every (shift, tile)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t key = (lane >> 4) * 4 + i;
+        const uint32_t kok = __shfl(ok, (int)key);
+        if (!kok)
+            continue;
+#pragma unroll
+        for (int t = 0; t < KT; t++) {
+            const uint32_t col = col0 + t;
+            if (col >= dim)
+                continue;
+            uint32_t v = (uint32_t)tot[t][i];
+            if (kok == 2)
+                v = 0u - v;
+            atomicAdd(&out[(size_t)(grp * 16 + key) * dim + col], v);
+        }
     }
 }
 
@@ -433,7 +546,44 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
         ((uintptr_t)d_table % 4) || ((uintptr_t)d_out % 4))
         return PIR_EINVAL;
 
-    const uint32_t Q = n_keys >= 16 ? 16 : (uint32_t)1 << ceil_log2(n_keys);
+    if (n_keys >= 16 && n >= 4 && dim <= 64) {
+        Geo3 g3;
+        g3.n = n;
+        g3.n_groups = (n_keys + 15) / 16;
+        uint32_t h = std::min<uint32_t>(HMAX3, n - 2);
+        // enough wave items to fill every CU several times
+        while (h > 3 && (((rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h)) * g3.n_groups) < 8192)
+            h--;
+        g3.h = h;
+        const uint64_t chunks = (rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h);
+        if (chunks * g3.n_groups >= ((uint64_t)1 << 31))
+            return PIR_ENOMEM;
+        g3.n_items = (uint32_t)(chunks * g3.n_groups);
+        const size_t count = (size_t)n_keys * dim;
+        const uint32_t fill_blocks = (uint32_t)std::min<size_t>((count + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks), dim3(256), 0, st, d_out, count);
+        const dim3 grid((g3.n_items + NW3 - 1) / NW3);
+#define PIR_LAUNCH_WAVES(KT, VEC)                                                                              \
+    hipLaunchKernelGGL((k_pir_waves<KT, VEC>), grid, dim3(NT3), 0, st, d_keys, n_keys, key_stride, d_table, rows, \
+                       dim, d_out, g3)
+        if (dim == 64)
+            PIR_LAUNCH_WAVES(4, true);
+        else if (dim == 32)
+            PIR_LAUNCH_WAVES(2, true);
+        else if (dim == 16)
+            PIR_LAUNCH_WAVES(1, true);
+        else if (dim < 16)
+            PIR_LAUNCH_WAVES(1, false);
+        else if (dim < 32)
+            PIR_LAUNCH_WAVES(2, false);
+        else
+            PIR_LAUNCH_WAVES(4, false);
+#undef PIR_LAUNCH_WAVES
+        hipError_t e = hipGetLastError();
+        return e == hipSuccess ? PIR_OK : fail_hip(e);
+    }
+
+    const uint32_t Q = n_keys >= QMAX ? QMAX : (uint32_t)1 << ceil_log2(n_keys);
     const uint32_t lgS_max = ceil_log2(NT / Q);
     const uint32_t groups = (n_keys + Q - 1) / Q;
     const uint32_t want = ceil_log2((2048 + groups - 1) / groups);
