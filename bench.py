@@ -39,22 +39,24 @@ PAPER_V100_QPS = 965.0  # Table 5, AES-128 row, same table shape and batch (cont
 #   bottom node (children are leaves, only bytes 0..3 needed):
 #                107 + 36 + 252 + 231 + 2*7 + 2 + 1                          = 643 VALU ops
 #   LDS table lookups: full node 40 + 160 + 148 = 348, bottom node 348 - 24 = 324
-#   contraction: dim x (multiply + add) VALU ops per leaf and key.
+# The share x table product of the batched kernel runs on the int8 matrix
+# cores, so the VALU figure counts the tree alone; the single-query kernel
+# does the product on the VALU (dim x (multiply + add) per leaf).
 VALU_FULL_NODE, VALU_BOTTOM_NODE = 694, 643
 LOOKUPS_FULL_NODE, LOOKUPS_BOTTOM_NODE = 348, 324
 PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x VALU lanes per clock x clock: 39.3 T int32 op/s
 PEAK_LDS_LOOKUPS = 256 * 32 * 2.4e9  # CUs x 128 B/clk of LDS reads / 4 B: 19.7 T lookups/s
 KERNEL_SOURCES = ["paper_2301_10904_amd/csrc/pir_device.hip", "paper_2301_10904_amd/csrc/aes_gfx950.h",
                   "paper_2301_10904_amd/csrc/aes_tables.h"]
-TRAFFIC_SUMMARY = ROOT / "profiles" / "k_pir_fused_2p20x64_b1024_traffic.json"
+TRAFFIC_SUMMARY = ROOT / "profiles" / "k_pir_waves_2p20x64_b1024_traffic.json"
 
 
-def algorithmic_work(n: int, keys: int, dim: int):
+def algorithmic_work(n: int, keys: int, dim: int, valu_product: bool = False):
     """(VALU ops, LDS lookups) of one launch over a full 2^n-leaf domain."""
     leaves = 1 << n
     bottom = leaves // 2
     full = bottom - 1
-    valu = keys * (full * VALU_FULL_NODE + bottom * VALU_BOTTOM_NODE + leaves * 2 * dim)
+    valu = keys * (full * VALU_FULL_NODE + bottom * VALU_BOTTOM_NODE + (leaves * 2 * dim if valu_product else 0))
     lds = keys * (full * LOOKUPS_FULL_NODE + bottom * LOOKUPS_BOTTOM_NODE)
     return valu, lds
 
@@ -151,7 +153,7 @@ def main():
 
     if args.pmc_summary:
         avg, scale, dispatches = pmc_summary(args.pmc_summary, copy_mib=args.calibrate_copy or 256)
-        out = {"kernel": "batched fused kernel (the 1024-key launch)", "dispatches": dispatches, "counters_avg": avg,
+        out = {"kernel": "k_pir_waves (the 1024-key launch)", "dispatches": dispatches, "counters_avg": avg,
                "copy_scale": scale, "kernel_digest": kernel_digest()}
         if "FETCH_SIZE" in avg and "WRITE_SIZE" in avg and len(scale) == 2:
             out["bytes_per_launch"] = int(1024 * (avg["FETCH_SIZE"] * scale["FETCH_SIZE"] +
@@ -240,7 +242,7 @@ def main():
     peak = PEAK_INT32_OPS / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
                 "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
-                "kernel": "k_pir_fused", "valu_ops_per_launch": valu_ops,
+                "kernel": "k_pir_waves", "valu_ops_per_launch": valu_ops,
                 "avg_launch_ms": round(kern_s * 1e3, 4), "kernel_digest": kernel_digest()}
     lds_rate = lookups / kern_s / 1e12
     roofline_lds = {"achieved": round(lds_rate, 3), "peak": round(PEAK_LDS_LOOKUPS / 1e12, 3),

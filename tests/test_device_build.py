@@ -1,0 +1,48 @@
+"""Build-time checks of the HIP device code (CPU only: hipcc cross-compiles).
+
+Every kernel that walks the tree reads its AES tables from LDS; if the
+compiler ever loses sight of those reads it may drop the table fill and the
+LDS allocation (a kernel would then read unallocated LDS).  The assembled
+kernels must each keep at least the 64 KiB table region, and none may spill
+to scratch memory.
+"""
+import re
+import shutil
+import subprocess
+
+import pytest
+
+from paper_2301_10904_amd import build as pbuild
+
+
+@pytest.fixture(scope="module")
+def device_asm(tmp_path_factory):
+    hipcc = pbuild.hipcc()
+    if not shutil.which(hipcc):
+        pytest.skip("hipcc not available")
+    out = tmp_path_factory.mktemp("asm") / "pir_device.s"
+    flags = [f for f in pbuild.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    subprocess.run([hipcc, *flags, f"-I{pbuild.ROOT / 'include'}", f"-I{pbuild.CSRC}",
+                    "--cuda-device-only", "-S", str(pbuild.CSRC / "pir_device.hip"), "-o", str(out)],
+                   check=True, capture_output=True)
+    return out.read_text()
+
+
+def kernel_metadata(asm):
+    meta = {}
+    for block in re.split(r"\n\s*- \.", asm):
+        name = re.search(r"\.name:\s+(\S+)", block)
+        lds = re.search(r"\.group_segment_fixed_size:\s+(\d+)", block)
+        scratch = re.search(r"\.private_segment_fixed_size:\s+(\d+)", block)
+        if name and lds and scratch:
+            meta[name.group(1)] = (int(lds.group(1)), int(scratch.group(1)))
+    return meta
+
+
+def test_tree_kernels_keep_their_lds_tables(device_asm):
+    meta = kernel_metadata(device_asm)
+    tree = {k: v for k, v in meta.items() if "k_pir_" in k}
+    assert len(tree) >= 10, sorted(meta)
+    for name, (lds, scratch) in tree.items():
+        assert lds >= 65536, f"{name}: LDS {lds} bytes, the AES tables need 65536"
+        assert scratch == 0, f"{name}: {scratch} bytes of scratch per lane"
