@@ -159,6 +159,31 @@ __device__ __forceinline__ void prf_pair(const uint32_t s[4], uint32_t a[4], uin
     b[3] = b3;
 }
 
+// PRF_s(c) alone, for a walk down one path (one block instead of two).
+__device__ __forceinline__ void prf_one(const uint32_t s[4], uint32_t c, uint32_t a[4], const Lanes &L)
+{
+    uint32_t k[4] = {s[0], s[1], s[2], s[3]}, kr[4];
+    a[0] = k[0];
+    a[1] = k[1];
+    a[2] = k[2];
+    a[3] = k[3] ^ (c << 24); // counter block c: byte 15 = c
+#pragma unroll
+    for (int r = 1; r <= 9; r++) {
+        next_key(k, pir_aes::RCON.v[r], L);
+#pragma unroll
+        for (int j = 0; j < 4; j++)
+            kr[j] = rot16(k[j]);
+        full_round(a, kr, L);
+    }
+    next_key(k, pir_aes::RCON.v[10], L);
+    uint32_t a0 = fcol(a[0], a[1], a[2], a[3], k[0], L), a1 = fcol(a[1], a[2], a[3], a[0], k[1], L);
+    uint32_t a2 = fcol(a[2], a[3], a[0], a[1], k[2], L), a3 = fcol(a[3], a[0], a[1], a[2], k[3], L);
+    a[0] = a0;
+    a[1] = a1;
+    a[2] = a2;
+    a[3] = a3;
+}
+
 // Only word 0 (bytes 0..3) of PRF_s(0) and PRF_s(1): what a leaf share uses.
 __device__ __forceinline__ void prf_pair_word0(const uint32_t s[4], uint32_t &y0, uint32_t &y1, const Lanes &L)
 {
@@ -171,12 +196,19 @@ __device__ __forceinline__ void prf_pair_word0(const uint32_t s[4], uint32_t &y0
     y1 = fcol(b[0], b[1], b[2], b[3], k0, L);
 }
 
-// Fill the LDS table region (called by every lane of the workgroup).
+// Fill the LDS table region (called by every lane of the workgroup): one
+// global load per half row, then eight 16-byte LDS writes of its 32 copies.
 __device__ __forceinline__ void fill_tables(uint32_t *tab, const uint32_t *te_global, uint32_t tid, uint32_t nthreads)
 {
-    for (uint32_t i = tid; i < AES_TAB_WORDS; i += nthreads) {
-        uint32_t v = te_global[i >> 6];
-        tab[i] = (i & 32) ? __builtin_amdgcn_alignbit(v, v, 24) : v; // rotl8 in the upper half
+    for (uint32_t i = tid; i < 512; i += nthreads) {
+        const uint32_t x = i >> 1, upper = i & 1;
+        uint32_t v = te_global[x];
+        v = upper ? __builtin_amdgcn_alignbit(v, v, 24) : v; // rotl8 in the upper half
+        uint4 *dst = reinterpret_cast<uint4 *>(tab + x * 64 + upper * 32);
+        const uint4 q = make_uint4(v, v, v, v);
+#pragma unroll
+        for (int j = 0; j < 8; j++)
+            dst[j] = q;
     }
 }
 

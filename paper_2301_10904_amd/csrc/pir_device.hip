@@ -95,6 +95,16 @@ __device__ __forceinline__ void children(const Lanes &L, const KeyView &K, const
     c1 = Seed{{b[0] ^ w1.x, b[1] ^ w1.y, b[2] ^ w1.z, b[3] ^ w1.w}};
 }
 
+// Child c of the node with seed s, codeword level d (Eq. (p3)), for descents.
+__device__ __forceinline__ Seed child_on_path(const Lanes &L, const KeyView &K, const Seed &s, uint32_t d, uint32_t c)
+{
+    const uint4 *q = reinterpret_cast<const uint4 *>(K.p + 32 + 64 * (size_t)(d - 1) + 32 * (s.w[0] & 1u) + 16 * c);
+    const uint4 w = *q;
+    uint32_t a[4];
+    prf_one(s.w, c, a, L);
+    return Seed{{a[0] ^ w.x, a[1] ^ w.y, a[2] ^ w.z, a[3] ^ w.w}};
+}
+
 __global__ void k_fill_zero(uint32_t *out, size_t count)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -111,8 +121,9 @@ struct Geometry {
     uint32_t n_chunks; // row chunks
 };
 
-// Q keys per group (Q <= QMAX); KCH column chunks of 64 (dim <= 64 KCH).
-template <int Q, int KCH>
+// Q keys per group (Q <= QMAX); KCH column chunks of 64 (dim <= 64 KCH);
+// VEC4: dim is a multiple of 4 (16-byte row segments are aligned).
+template <int Q, int KCH, bool VEC4>
 __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ keys, uint32_t n_keys,
                                                   uint32_t stride, const uint32_t *__restrict__ table,
                                                   uint64_t rows, uint32_t dim, uint32_t *__restrict__ out,
@@ -155,11 +166,8 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     if (tid < Q && sm.keyok[tid]) {
         const KeyView K{keys + (size_t)(grp * Q + tid) * stride};
         Seed s = sm.u.bfs[tid];
-        for (uint32_t d = 1; d <= dtop; d++) {
-            Seed c0, c1;
-            children(L, K, s, d, c0, c1);
-            s = ((row_base >> (g.n - d)) & 1) ? c1 : c0;
-        }
+        for (uint32_t d = 1; d <= dtop; d++)
+            s = child_on_path(L, K, s, d, (uint32_t)(row_base >> (g.n - d)) & 1u);
         sm.u.bfs[tid] = s;
     }
     __syncthreads();
@@ -197,12 +205,23 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     for (int i = 0; i < HMAX; i++)
         right[i] = Seed{{0, 0, 0, 0}};
 
-    uint32_t acc[Q][KCH];
+    // WIDE: few accumulators per column; a lane then owns 4 columns of one of
+    // 4 row slots, otherwise one column of every row
+    constexpr bool WIDE = Q * KCH <= 4;
+    uint32_t acc[WIDE ? 1 : Q][WIDE ? 1 : KCH];
+    uint32_t accw[WIDE ? Q : 1][WIDE ? KCH : 1][4];
 #pragma unroll
-    for (int i = 0; i < Q; i++)
+    for (int i = 0; i < (WIDE ? 1 : Q); i++)
 #pragma unroll
-        for (int c = 0; c < KCH; c++)
+        for (int c = 0; c < (WIDE ? 1 : KCH); c++)
             acc[i][c] = 0;
+#pragma unroll
+    for (int i = 0; i < (WIDE ? Q : 1); i++)
+#pragma unroll
+        for (int c = 0; c < (WIDE ? KCH : 1); c++)
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                accw[i][c][e] = 0;
 
     uint32_t(*sh)[Q] = reinterpret_cast<uint32_t(*)[Q]>(sm.u.sh);
     for (uint32_t m = 0; m < steps; m++) {
@@ -240,23 +259,86 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             sh[2 * ln + 1][q] = y1;
         }
         __syncthreads();
-        for (uint32_t i = wave; i < 2 * S_used; i += NW) {
-            const uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
-            if (row >= rows)
-                continue;
-            const uint32_t *trow = table + row * dim;
-            uint32_t tv[KCH];
+        const uint32_t n_rows = 2 * S_used;
+        if (WIDE) {
+            // lane = (row slot rs = lane / 16, column group cg = lane mod 16):
+            // one 16-byte load covers 4 columns, a wave covers 4 rows per
+            // load, and U loads are in flight before any is used
+            constexpr int U = KCH >= 4 ? 1 : 4 / KCH;
+            const uint32_t rs = lane >> 4, cg = lane & 15;
+            for (uint32_t i0 = wave * 4; i0 < n_rows; i0 += NW * 4 * U) {
+                uint32_t tv[U][KCH][4];
 #pragma unroll
-            for (int c = 0; c < KCH; c++) {
-                const uint32_t col = lane + 64 * c;
-                tv[c] = col < dim ? trow[col] : 0u;
+                for (int u = 0; u < U; u++) {
+                    const uint32_t i = i0 + u * NW * 4 + rs;
+                    const uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
+                    const bool ok = i < n_rows && row < rows;
+                    const uint32_t *trow = table + (ok ? row : 0) * dim;
+#pragma unroll
+                    for (int c = 0; c < KCH; c++) {
+                        const uint32_t col = 64 * c + 4 * cg;
+                        if (VEC4) {
+                            const uint4 x = col < dim ? *reinterpret_cast<const uint4 *>(trow + col) : make_uint4(0, 0, 0, 0);
+                            tv[u][c][0] = ok ? x.x : 0u;
+                            tv[u][c][1] = ok ? x.y : 0u;
+                            tv[u][c][2] = ok ? x.z : 0u;
+                            tv[u][c][3] = ok ? x.w : 0u;
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                const uint32_t cc = col + e;
+                                const uint32_t x = trow[cc < dim ? cc : dim - 1];
+                                tv[u][c][e] = (ok && cc < dim) ? x : 0u;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const uint32_t i = i0 + u * NW * 4 + rs;
+                    const uint32_t ii = i < n_rows ? i : 0; // masked rows add zero
+#pragma unroll
+                    for (int qq = 0; qq < Q; qq++) {
+                        const uint32_t y = sh[ii][qq];
+#pragma unroll
+                        for (int c = 0; c < KCH; c++)
+#pragma unroll
+                            for (int e = 0; e < 4; e++)
+                                accw[qq][c][e] += y * tv[u][c][e];
+                    }
+                }
             }
+        } else {
+            // lane = column: U rows per round, their words loaded together
+            // (clamped addresses, masked values) so the loads overlap
+            constexpr int U = (Q * KCH >= 32) ? 2 : (Q * KCH >= 8 ? 4 : 8);
+            for (uint32_t i0 = wave; i0 < n_rows; i0 += NW * U) {
+                uint32_t tv[U][KCH];
 #pragma unroll
-            for (int qq = 0; qq < Q; qq++) {
-                const uint32_t y = sh[i][qq];
+                for (int u = 0; u < U; u++) {
+                    const uint32_t i = i0 + u * NW;
+                    const uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
+                    const bool ok = i < n_rows && row < rows;
+                    const uint32_t *trow = table + (ok ? row : 0) * dim;
 #pragma unroll
-                for (int c = 0; c < KCH; c++)
-                    acc[qq][c] += y * tv[c];
+                    for (int c = 0; c < KCH; c++) {
+                        const uint32_t col = lane + 64 * c;
+                        const uint32_t x = trow[col < dim ? col : dim - 1];
+                        tv[u][c] = (ok && col < dim) ? x : 0u;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const uint32_t i = i0 + u * NW;
+                    const uint32_t ii = i < n_rows ? i : 0;
+#pragma unroll
+                    for (int qq = 0; qq < Q; qq++) {
+                        const uint32_t y = sh[ii][qq];
+#pragma unroll
+                        for (int c = 0; c < KCH; c++)
+                            acc[qq][c] += y * tv[u][c];
+                    }
+                }
             }
         }
     }
@@ -267,14 +349,27 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     for (uint32_t i = tid; i < Q * dim; i += NT)
         s_acc[i] = 0;
     __syncthreads();
+    if (WIDE) {
 #pragma unroll
-    for (int qq = 0; qq < Q; qq++)
+        for (int qq = 0; qq < (WIDE ? Q : 1); qq++)
 #pragma unroll
-        for (int c = 0; c < KCH; c++) {
-            const uint32_t col = lane + 64 * c;
-            if (col < dim)
-                atomicAdd(&s_acc[qq * dim + col], acc[qq][c]);
-        }
+            for (int c = 0; c < (WIDE ? KCH : 1); c++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t col = 64 * c + 4 * (lane & 15) + e;
+                    if (col < dim)
+                        atomicAdd(&s_acc[qq * dim + col], accw[qq][c][e]);
+                }
+    } else {
+#pragma unroll
+        for (int qq = 0; qq < (WIDE ? 1 : Q); qq++)
+#pragma unroll
+            for (int c = 0; c < (WIDE ? 1 : KCH); c++) {
+                const uint32_t col = lane + 64 * c;
+                if (col < dim)
+                    atomicAdd(&s_acc[qq * dim + col], acc[qq][c]);
+            }
+    }
     __syncthreads();
     for (uint32_t i = tid; i < Q * dim; i += NT) {
         const uint32_t qq = i / dim, col = i % dim;
@@ -405,11 +500,8 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
     Seed node{{0, 0, 0, 0}};
     if (active) {
         node = K.root();
-        for (uint32_t d = 1; d + h <= g.n; d++) {
-            Seed c0, c1;
-            children(L, K, node, d, c0, c1);
-            node = ((lane_row0 >> (g.n - d)) & 1) ? c1 : c0;
-        }
+        for (uint32_t d = 1; d + h <= g.n; d++)
+            node = child_on_path(L, K, node, d, (uint32_t)(lane_row0 >> (g.n - d)) & 1u);
     }
     const uint32_t d0 = g.n - h;
     Seed right[HMAX3];
@@ -514,15 +606,27 @@ static void launch_q(uint32_t kch, dim3 grid, hipStream_t st, const uint8_t *key
                      uint32_t stride, const uint32_t *table, uint64_t rows, uint32_t dim, uint32_t *out,
                      const Geometry &g)
 {
-    if (kch == 1)
-        hipLaunchKernelGGL((k_pir_fused<Q, 1>), grid, dim3(NT), 0, st, keys, n_keys, stride, table, rows,
-                           dim, out, g);
-    else if (kch == 2)
-        hipLaunchKernelGGL((k_pir_fused<Q, 2>), grid, dim3(NT), 0, st, keys, n_keys, stride, table, rows,
-                           dim, out, g);
-    else
-        hipLaunchKernelGGL((k_pir_fused<Q, 4>), grid, dim3(NT), 0, st, keys, n_keys, stride, table, rows,
-                           dim, out, g);
+#define PIR_LAUNCH_FUSED(KCH, V4)                                                                                 \
+    hipLaunchKernelGGL((k_pir_fused<Q, KCH, V4>), grid, dim3(NT), 0, st, keys, n_keys, stride, table, rows, dim, \
+                       out, g)
+    const bool v4 = dim % 4 == 0;
+    if (kch == 1) {
+        if (v4)
+            PIR_LAUNCH_FUSED(1, true);
+        else
+            PIR_LAUNCH_FUSED(1, false);
+    } else if (kch == 2) {
+        if (v4)
+            PIR_LAUNCH_FUSED(2, true);
+        else
+            PIR_LAUNCH_FUSED(2, false);
+    } else {
+        if (v4)
+            PIR_LAUNCH_FUSED(4, true);
+        else
+            PIR_LAUNCH_FUSED(4, false);
+    }
+#undef PIR_LAUNCH_FUSED
 }
 
 static int fail_hip(hipError_t e)
@@ -586,7 +690,7 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
     const uint32_t Q = n_keys >= QMAX ? QMAX : (uint32_t)1 << ceil_log2(n_keys);
     const uint32_t lgS_max = ceil_log2(NT / Q);
     const uint32_t groups = (n_keys + Q - 1) / Q;
-    const uint32_t want = ceil_log2((2048 + groups - 1) / groups);
+    const uint32_t want = ceil_log2((512 + groups - 1) / groups); // about one round of workgroup slots
     uint32_t H = n > want ? n - want : 1;
     H = std::min(H, lgS_max + (uint32_t)HMAX);
     H = std::max(H, std::min(n, lgS_max + 1));
