@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <vector>
 
 #include "aes_gfx950.h"
 #include "aes_tables.h"
@@ -409,13 +410,6 @@ constexpr int NW3 = 8;             // waves per workgroup (two workgroups per CU
 constexpr int HMAX3 = 9;           // largest per-lane subtree height of the wave kernel
 constexpr int NT3 = 64 * NW3;
 
-struct Geo3 {
-    uint32_t n;        // log2 of the key domain
-    uint32_t h;        // per-lane subtree height (chunk = 4 * 2^h rows)
-    uint32_t n_groups; // key groups of 16
-    uint32_t n_items;  // n_groups * chunks
-};
-
 __device__ __forceinline__ uint32_t balanced(uint32_t x) { return (x + 0x80808080u) ^ 0x80808080u; }
 
 // digits of x arranged for shift s: byte j holds d_{s-j} (0 where j > s)
@@ -465,10 +459,23 @@ __device__ __forceinline__ void load_cols(const uint32_t *__restrict__ table, ui
     }
 }
 
+// One table's share of a wave-kernel launch.
+struct WaveTask {
+    const uint32_t *table; // row-major uint32 [rows][dim]
+    const uint8_t *keys;   // this table's first key
+    uint32_t *out;         // this table's first answer word
+    uint64_t rows;
+    uint32_t dim, n_keys, n, h, n_groups, item_begin;
+};
+constexpr int MAX_TASKS = 16;
+struct WaveTasks {
+    WaveTask t[MAX_TASKS];
+    uint32_t count, n_items;
+};
+
 template <int KT, bool VEC>
-__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_waves(const uint8_t *__restrict__ keys, uint32_t n_keys,
-                                                   uint32_t stride, const uint32_t *__restrict__ table,
-                                                   uint64_t rows, uint32_t dim, uint32_t *__restrict__ out, Geo3 g)
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_waves(const WaveTasks tasks,
+                                                                                           uint32_t stride)
 {
     __shared__ uint32_t tab[AES_TAB_WORDS];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
@@ -476,9 +483,19 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
     fill_tables(tab, c_TE.v, tid, NT3);
     __syncthreads();
 
-    const uint32_t item = blockIdx.x * NW3 + wave;
-    if (item >= g.n_items)
+    const uint32_t item0 = blockIdx.x * NW3 + wave;
+    if (item0 >= tasks.n_items)
         return; // whole wave; no barrier follows
+    uint32_t ti = 0; // the table this item belongs to (tasks are in item order)
+    while (ti + 1 < tasks.count && item0 >= tasks.t[ti + 1].item_begin)
+        ti++;
+    const WaveTask &g = tasks.t[ti];
+    const uint32_t item = item0 - g.item_begin;
+    const uint8_t *__restrict__ keys = g.keys;
+    const uint32_t *__restrict__ table = g.table;
+    uint32_t *__restrict__ out = g.out;
+    const uint64_t rows = g.rows;
+    const uint32_t dim = g.dim, n_keys = g.n_keys;
     const uint32_t grp = item % g.n_groups, chunk = item / g.n_groups;
     const uint32_t q = lane & 15, sub = lane >> 4;
     const uint32_t kq = grp * 16 + q;
@@ -635,6 +652,69 @@ static int fail_hip(hipError_t e)
     return PIR_EHIP;
 }
 
+// Wave-kernel launch for up to MAX_TASKS tables of one column class (KT, VEC).
+// Fills h, n_groups and item_begin of every task; clears the outputs first.
+static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipStream_t st, uint64_t min_items)
+{
+    WaveTasks W;
+    uint64_t items = 0;
+    for (uint32_t i = 0; i < count; i++) {
+        WaveTask &t = ts[i];
+        t.n_groups = (t.n_keys + 15) / 16;
+        uint32_t h = std::min<uint32_t>(HMAX3, t.n - 2);
+        // enough wave items to fill every CU several times (single table)
+        while (count == 1 && h > 3 &&
+               ((t.rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h)) * t.n_groups < min_items)
+            h--;
+        t.h = h;
+        const uint64_t chunks = (t.rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h);
+        t.item_begin = (uint32_t)items;
+        items += chunks * t.n_groups;
+        if (items >= ((uint64_t)1 << 31))
+            return PIR_ENOMEM;
+        W.t[i] = t;
+    }
+    W.count = count;
+    W.n_items = (uint32_t)items;
+    for (uint32_t i = 0; i < count; i++) {
+        const size_t words = (size_t)ts[i].n_keys * ts[i].dim;
+        const uint32_t blocks = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
+        hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, ts[i].out, words);
+    }
+    if (items == 0)
+        return PIR_OK;
+    const dim3 grid((uint32_t)((items + NW3 - 1) / NW3));
+    const uint32_t dim = ts[0].dim;
+#define PIR_LAUNCH_WAVES(KT, VEC) hipLaunchKernelGGL((k_pir_waves<KT, VEC>), grid, dim3(NT3), 0, st, W, key_stride)
+    if (dim == 64)
+        PIR_LAUNCH_WAVES(4, true);
+    else if (dim == 32)
+        PIR_LAUNCH_WAVES(2, true);
+    else if (dim == 16)
+        PIR_LAUNCH_WAVES(1, true);
+    else if (dim < 16)
+        PIR_LAUNCH_WAVES(1, false);
+    else if (dim < 32)
+        PIR_LAUNCH_WAVES(2, false);
+    else
+        PIR_LAUNCH_WAVES(4, false);
+#undef PIR_LAUNCH_WAVES
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? PIR_OK : fail_hip(e);
+}
+
+// Column class of the wave kernel: tables in one launch must share it.
+static int wave_class(uint32_t dim)
+{
+    if (dim == 64) return 0;
+    if (dim == 32) return 1;
+    if (dim == 16) return 2;
+    if (dim < 16) return 3;
+    if (dim < 32) return 4;
+    if (dim <= 64) return 5;
+    return -1;
+}
+
 // Validates one table's call and enqueues its kernels.
 static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, const uint32_t *d_table,
                       uint64_t rows, uint32_t dim, uint32_t *d_out, hipStream_t st)
@@ -650,41 +730,16 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
         ((uintptr_t)d_table % 4) || ((uintptr_t)d_out % 4))
         return PIR_EINVAL;
 
-    if (n_keys >= 16 && n >= 4 && dim <= 64) {
-        Geo3 g3;
-        g3.n = n;
-        g3.n_groups = (n_keys + 15) / 16;
-        uint32_t h = std::min<uint32_t>(HMAX3, n - 2);
-        // enough wave items to fill every CU several times
-        while (h > 3 && (((rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h)) * g3.n_groups) < 8192)
-            h--;
-        g3.h = h;
-        const uint64_t chunks = (rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h);
-        if (chunks * g3.n_groups >= ((uint64_t)1 << 31))
-            return PIR_ENOMEM;
-        g3.n_items = (uint32_t)(chunks * g3.n_groups);
-        const size_t count = (size_t)n_keys * dim;
-        const uint32_t fill_blocks = (uint32_t)std::min<size_t>((count + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks), dim3(256), 0, st, d_out, count);
-        const dim3 grid((g3.n_items + NW3 - 1) / NW3);
-#define PIR_LAUNCH_WAVES(KT, VEC)                                                                              \
-    hipLaunchKernelGGL((k_pir_waves<KT, VEC>), grid, dim3(NT3), 0, st, d_keys, n_keys, key_stride, d_table, rows, \
-                       dim, d_out, g3)
-        if (dim == 64)
-            PIR_LAUNCH_WAVES(4, true);
-        else if (dim == 32)
-            PIR_LAUNCH_WAVES(2, true);
-        else if (dim == 16)
-            PIR_LAUNCH_WAVES(1, true);
-        else if (dim < 16)
-            PIR_LAUNCH_WAVES(1, false);
-        else if (dim < 32)
-            PIR_LAUNCH_WAVES(2, false);
-        else
-            PIR_LAUNCH_WAVES(4, false);
-#undef PIR_LAUNCH_WAVES
-        hipError_t e = hipGetLastError();
-        return e == hipSuccess ? PIR_OK : fail_hip(e);
+    if (n_keys >= 16 && n >= 3 && dim <= 64) {
+        WaveTask t;
+        t.table = d_table;
+        t.keys = d_keys;
+        t.out = d_out;
+        t.rows = rows;
+        t.dim = dim;
+        t.n_keys = n_keys;
+        t.n = n;
+        return launch_waves(&t, 1, key_stride, st, 8192);
     }
 
     const uint32_t Q = n_keys >= QMAX ? QMAX : (uint32_t)1 << ceil_log2(n_keys);
@@ -748,16 +803,43 @@ int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t
         if (key_stride % 16 || key_stride < dpf_key_size(n))
             return PIR_EINVAL;
     }
+    // tables the wave kernel takes go out grouped by column class, up to
+    // MAX_TASKS per launch; the rest one by one
+    std::vector<WaveTask> cls[6];
     size_t key_off = 0, out_off = 0;
     for (uint32_t t = 0; t < n_tables; t++) {
         const pir_table_t &T = tables[t];
-        int st = answer_one(d_keys + key_off * key_stride, T.n_keys, key_stride, T.d_table, T.rows, T.dim,
-                            d_out + out_off, (hipStream_t)stream);
-        if (st != PIR_OK)
-            return st;
+        const uint8_t *kp = d_keys + key_off * key_stride;
+        uint32_t *op = d_out + out_off;
         key_off += T.n_keys;
         out_off += (size_t)T.n_keys * T.dim;
+        if (T.n_keys == 0)
+            continue;
+        const uint32_t n = T.rows <= 2 ? 1 : ceil_log2(T.rows);
+        const int c = wave_class(T.dim);
+        if (n >= 3 && c >= 0) {
+            WaveTask w;
+            w.table = T.d_table;
+            w.keys = kp;
+            w.out = op;
+            w.rows = T.rows;
+            w.dim = T.dim;
+            w.n_keys = T.n_keys;
+            w.n = n;
+            cls[c].push_back(w);
+        } else {
+            int st = answer_one(kp, T.n_keys, key_stride, T.d_table, T.rows, T.dim, op, (hipStream_t)stream);
+            if (st != PIR_OK)
+                return st;
+        }
     }
+    for (auto &v : cls)
+        for (size_t i = 0; i < v.size(); i += MAX_TASKS) {
+            const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, v.size() - i);
+            int st = launch_waves(v.data() + i, cnt, key_stride, (hipStream_t)stream, 8192);
+            if (st != PIR_OK)
+                return st;
+        }
     return PIR_OK;
 }
 

@@ -201,3 +201,111 @@ def test_answer_multi_ragged(O, pirmod):
     for v, e in zip(views, expect):
         if e is not None:
             assert (v.cpu().numpy().view(np.uint32) == e).all()
+
+
+def sparse_answers(O, keys, support_rows, support_vals):
+    """Per-server answers over a table that is zero except `support_rows`:
+    sum_j Eval(key, j) * T[j] over the support only, with point evaluation."""
+    out = np.zeros((len(keys), support_vals.shape[1]), np.uint64)
+    for q, key in enumerate(keys):
+        for j, row in zip(support_rows, support_vals):
+            y = np.uint64(O.eval_point(key, int(j)))
+            out[q] = (out[q] + y * row.astype(np.uint64)) & 0xFFFFFFFF
+    return out.astype(np.uint32)
+
+
+def make_sparse(rows, dim, seed, n_support, device):
+    import torch
+
+    rng = np.random.default_rng([seed, 77])
+    support = np.sort(rng.choice(rows, n_support, replace=False))
+    support[0] = rows - 1
+    vals = W.table_rows_np(support, dim, seed)
+    T = torch.zeros((rows, dim), dtype=torch.int32, device=device)
+    T[torch.from_numpy(support).to(device)] = torch.from_numpy(vals.view(np.int32)).to(device)
+    return T, np.sort(support), vals[np.argsort(support)]
+
+
+def test_multi_table_ragged_zipf(O, pirmod):
+    """Eight tables of 2^16 .. 2^23 rows x 32 uint32 (about 2 GiB), ragged
+    batches of 32..1024 queries (both servers' keys), Zipf(1.05) indices, one
+    call.  Every reconstruction equals T_t[alpha]; per-server answers are
+    bit-exact on sparse copies of the two largest tables (all their keys) and
+    against the full oracle on samples of the smallest table."""
+    import torch
+
+    seed = 3
+    sizes = W.ragged_batch_sizes(8, seed)
+    tables, counts, keysets, alphas = [], [], [], []
+    for t in range(8):
+        rows = 1 << (16 + t)
+        tables.append(W.make_table(rows, 32, seed + t, device="cuda"))
+        a = W.zipf_indices(rows, int(sizes[t]), seed + t)
+        K0, K1 = oracle_keys(O, 16 + t, a, seed + t)
+        keysets.append(np.concatenate([K0, K1]))
+        counts.append(2 * int(sizes[t]))
+        alphas.append(a)
+    stride = (max(k.shape[1] for k in keysets) + 15) // 16 * 16
+    keys = np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keysets])
+    keys_dev = torch.from_numpy(keys).cuda()
+    _, views = pirmod.answer_multi(tables, counts, keys_dev)
+    torch.cuda.synchronize()
+    for t in range(8):
+        got = views[t].cpu().numpy().view(np.uint32)
+        want = W.table_rows_np(alphas[t], 32, seed + t)
+        B = int(sizes[t])
+        recon = (got[:B].astype(np.uint64) + got[B:]) & 0xFFFFFFFF
+        assert (recon.astype(np.uint32) == want).all(), t
+    # full oracle on a sample of the smallest table
+    T0 = tables[0].cpu().numpy().view(np.uint32)
+    sample = [0, 1, counts[0] - 1]
+    want = O.answer_batch(keysets[0][sample], T0, nthreads=cpu_threads())
+    assert (views[0].cpu().numpy().view(np.uint32)[sample] == want).all()
+    # sparse copies of the two largest tables: every key, per server
+    for t in (6, 7):
+        rows = 1 << (16 + t)
+        Ts, sup, vals = make_sparse(rows, 32, seed + t, 12, "cuda")
+        sub = [tables[i] if i != t else Ts for i in range(8)]
+        _, v2 = pirmod.answer_multi(sub, counts, keys_dev)
+        torch.cuda.synchronize()
+        got = v2[t].cpu().numpy().view(np.uint32)
+        assert (got == sparse_answers(O, keysets[t], sup, vals)).all(), t
+        del Ts
+    del tables
+    torch.cuda.empty_cache()
+
+
+def test_large_table_2p25_x64(O, pirmod):
+    """One table of 2^25 rows x 64 uint32 (8 GiB) resident in HBM, 512 key
+    pairs with uniform indices: every reconstruction equals T[alpha], and on a
+    sparse copy of the same shape every per-server answer is bit-exact."""
+    import torch
+
+    rows, dim, pairs, seed = 1 << 25, 64, 512, 4
+    T = W.make_table(rows, dim, seed, device="cuda")
+    alphas = W.uniform_indices(rows, pairs, seed)
+    K0, K1 = oracle_keys(O, 25, alphas, seed)
+    keys = np.concatenate([K0, K1])
+    keys_dev = torch.from_numpy(keys).cuda()
+    out = pirmod.answer(keys_dev, T)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    want = W.table_rows_np(alphas, dim, seed)
+    recon = (got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF
+    assert (recon.astype(np.uint32) == want).all()
+    del T, out
+    torch.cuda.empty_cache()
+    Ts, sup, vals = make_sparse(rows, dim, seed, 8, "cuda")
+    out = pirmod.answer(keys_dev, Ts)
+    torch.cuda.synchronize()
+    sample = np.arange(0, 2 * pairs, 37)
+    got = out.cpu().numpy().view(np.uint32)
+    assert (got[sample] == sparse_answers(O, keys[sample], sup, vals)).all()
+    # reconstruction on the sparse table: T[alpha] if alpha is in the support, else 0
+    dense_rows = {int(j): v for j, v in zip(sup, vals)}
+    for p in range(pairs):
+        r = (got[p].astype(np.uint64) + got[pairs + p]) & 0xFFFFFFFF
+        w = dense_rows.get(int(alphas[p]), np.zeros(dim, np.uint32))
+        assert (r.astype(np.uint32) == w).all()
+    del Ts
+    torch.cuda.empty_cache()
