@@ -144,6 +144,10 @@ def main():
     ap.add_argument("--single-steps", type=int, default=50)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", default="batch", choices=["batch", "small", "multi", "large", "serve"],
+                    help="batch: 2^20 x 64, 512 pairs (the default line); small: 2^14 x 16, one pair; "
+                         "multi: 8 tables 2^16..2^23 x 32, ragged Zipf batches in one call; "
+                         "large: 2^25 x 64 (8 GiB), 512..2048 pairs; serve: Poisson request loop over 4 tables")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="summarise rocprofv3 --pmc counter CSVs of this benchmark and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -173,6 +177,8 @@ def main():
     from paper_2301_10904_amd import workloads as W
 
     pir.load()
+    if args.mode != "batch":
+        return other_modes(args)
     dev = torch.device("cuda:0")
     rows, dim, pairs = 1 << args.log_rows, args.dim, args.pairs
     n = pir.log_domain(rows)
@@ -285,6 +291,154 @@ def main():
     print(json.dumps(res), flush=True)
     if not recon_ok:
         sys.exit(1)
+
+
+def time_launches(fn, steps, warmup):
+    """Average seconds per call of fn() (event-bracketed on the current stream) and per-call ms."""
+    import torch
+
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    t0 = time.perf_counter()
+    for e0, e1 in evs:
+        e0.record()
+        fn()
+        e1.record()
+    torch.cuda.synchronize()
+    return (time.perf_counter() - t0) / steps, [a.elapsed_time(b) for a, b in evs]
+
+
+def other_modes(args):
+    """The other workloads: one JSON line each (not the driver's default line)."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    line = {"metric": METRIC, "unit": "server queries/s", "n_gpus": 1, "higher_is_better": True,
+            "dtype": "u32", "data": "synthetic", "mode": args.mode}
+    if args.mode == "small":
+        rows, dim = 1 << 14, 16
+        T = W.make_table(rows, dim, 1, device=dev)
+        a = W.uniform_indices(rows, 1, 1)
+        K0, K1 = pir.gen_batch(14, a, W.key_seeds(1, 1))
+        keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
+        out = torch.empty((2, dim), dtype=torch.int32, device=dev)
+        sec, ms = time_launches(lambda: pir.answer(keys, T, out), 200, 10)
+        got = out.cpu().numpy().view(np.uint32)
+        ok = bool((pir.reconstruct(got[0], got[1]) == W.table_rows_np(a, dim, 1)[0]).all())
+        line.update(value=round(2 / sec, 1), exact=ok, p50_ms=round(percentile(ms, 50), 4),
+                    p99_ms=round(percentile(ms, 99), 4),
+                    config={"workload": "one table 2^14 x 16 uint32, one key pair per call"})
+    elif args.mode == "multi":
+        seed = 3
+        sizes = W.ragged_batch_sizes(8, seed)
+        tables, counts, keys_l, alphas = [], [], [], []
+        for t in range(8):
+            rows = 1 << (16 + t)
+            tables.append(W.make_table(rows, 32, seed + t, device=dev))
+            a = W.zipf_indices(rows, int(sizes[t]), seed + t)
+            K0, K1 = pir.gen_batch(16 + t, a, W.key_seeds(len(a), seed + t))
+            keys_l.append(np.concatenate([K0, K1]))
+            counts.append(2 * int(sizes[t]))
+            alphas.append(a)
+        stride = (max(k.shape[1] for k in keys_l) + 15) // 16 * 16
+        keys = torch.from_numpy(np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keys_l])).to(dev)
+        out, views = pir.answer_multi(tables, counts, keys)
+        sec, ms = time_launches(lambda: pir.answer_multi(tables, counts, keys, out=out), 5, 1)
+        ok = True
+        for t in range(8):
+            got = views[t].cpu().numpy().view(np.uint32)
+            B = counts[t] // 2
+            rec = ((got[:B].astype(np.uint64) + got[B:]) & 0xFFFFFFFF).astype(np.uint32)
+            ok &= bool((rec == W.table_rows_np(alphas[t], 32, seed + t)).all())
+        line.update(value=round(sum(counts) / sec, 1), exact=ok, ms_per_call=round(sec * 1e3, 3),
+                    config={"workload": "8 tables 2^16..2^23 rows x 32 uint32 (2 GiB), ragged batches of "
+                                        "32..1024 queries (both servers' keys), Zipf(1.05), one call",
+                            "queries_per_table": [int(x) for x in sizes], "keys_per_call": sum(counts)})
+    elif args.mode == "large":
+        rows, dim, seed = 1 << 25, 64, 4
+        T = W.make_table(rows, dim, seed, device=dev)
+        res = {}
+        for pairs in (512, 1024, 2048):
+            a = W.uniform_indices(rows, pairs, seed)
+            K0, K1 = pir.gen_batch(25, a, W.key_seeds(pairs, seed))
+            keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
+            out = torch.empty((2 * pairs, dim), dtype=torch.int32, device=dev)
+            sec, ms = time_launches(lambda: pir.answer(keys, T, out), 2, 1)
+            got = out.cpu().numpy().view(np.uint32)
+            rec = ((got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF).astype(np.uint32)
+            res[2 * pairs] = {"server_qps": round(2 * pairs / sec, 1), "ms": round(sec * 1e3, 2),
+                              "exact": bool((rec == W.table_rows_np(a, dim, seed)).all())}
+        k1 = keys[:1].contiguous()
+        o1 = torch.empty((1, dim), dtype=torch.int32, device=dev)
+        sec1, ms1 = time_launches(lambda: pir.answer(k1, T, o1), 20, 3)
+        line.update(value=res[4096]["server_qps"], batches=res,
+                    single_query={"qps": round(1 / sec1, 1), "p50_ms": round(percentile(ms1, 50), 3),
+                                  "p99_ms": round(percentile(ms1, 99), 3)},
+                    config={"workload": "one table 2^25 x 64 uint32 (8 GiB) resident, 1024/2048/4096 keys"})
+    else:
+        line.update(serve_sweep(args))
+    print(json.dumps(line), flush=True)
+
+
+def serve_sweep(args):
+    """Poisson arrivals over 4 resident tables (2^18, 2^20, 2^22, 2^24 rows x 32 uint32)."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+    from paper_2301_10904_amd.serve import PirServer
+
+    dev = torch.device("cuda:0")
+    logs = [18, 20, 22, 24]
+    srv = PirServer(hbm_budget_bytes=4 << 30, max_batch=1024, max_queue=8192, max_inflight=3)
+    pool, pool_alpha = [], []
+    for i, lg in enumerate(logs):
+        T = W.make_table(1 << lg, 32, 50 + i, device=dev)
+        assert srv.admit_table(T) == i
+        a = W.uniform_indices(1 << lg, 512, 50 + i)
+        K0, K1 = pir.gen_batch(lg, a, W.key_seeds(512, 50 + i))
+        pool.append(np.concatenate([K0, K1]))
+        pool_alpha.append(np.concatenate([a, a]))
+    stride = (max(k.shape[1] for k in pool) + 15) // 16 * 16
+    pool = [np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in pool]
+    bad = []
+
+    def check(t, ki, row):
+        # the served share and its partner's share (answered directly) reconstruct T[alpha]
+        partner = ki + 512 if ki < 512 else ki - 512
+        pk = torch.from_numpy(pool[t][partner:partner + 1]).to(dev)
+        other = pir.answer(pk, srv.tables[t][0]).cpu().numpy().view(np.uint32)[0]
+        want = W.table_rows_np([pool_alpha[t][ki]], 32, 50 + t)[0]
+        if not (pir.reconstruct(row, other) == want).all():
+            bad.append((t, int(ki), int(np.sum(pir.reconstruct(row, other) != want))))
+
+    runs = []
+    dur = 1.5
+    for mix in ("uniform", "inv_rows"):
+        w = np.ones(4) if mix == "uniform" else np.array([1.0 / (1 << lg) for lg in logs])
+        w = w / w.sum()
+        for rate in (20000, 50000, 100000, 200000):
+            n = int(rate * dur)
+            arr = W.poisson_arrivals(rate, n, 7)
+            rng = np.random.default_rng([rate, len(mix)])
+            tids = rng.choice(4, n, p=w)
+            kidx = rng.integers(0, 1024, n)
+            stats = srv.run(arr, tids, pool, kidx, stride, check=check)
+            r = stats.summary()
+            r.update(mix=mix, offered_qps=rate)
+            runs.append(r)
+    return {"value": max(r["sustained_qps"] for r in runs), "exact": not bad, "check_failures": bad[:8],
+            "serve": runs,
+            "config": {"workload": "4 resident tables 2^18, 2^20, 2^22, 2^24 rows x 32 uint32 (2.7 GiB), "
+                                   "Poisson arrivals 20k..200k requests/s, one key per request, "
+                                   "batched by table (up to 1024 per table per batch, 3 batches in flight), "
+                                   "queue bound 8192 per table",
+                       "duration_s": dur}}
 
 
 if __name__ == "__main__":

@@ -309,3 +309,36 @@ def test_large_table_2p25_x64(O, pirmod):
         assert (r.astype(np.uint32) == w).all()
     del Ts
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("pairs,dim", [(1, 64), (1, 32), (2, 64), (3, 16), (7, 32)])
+def test_small_batches_deep_tree(O, pirmod, pairs, dim):
+    """Fewer than 16 keys on a 2^18-row table: the small-batch kernel with a
+    per-lane walk of height > 1, bit-exact against the full oracle."""
+    rows, seed = 1 << 18, 11 + pairs
+    T = W.make_table(rows, dim, seed)
+    alphas = W.uniform_indices(rows, pairs, seed)
+    K0, K1 = oracle_keys(O, 18, alphas, seed)
+    keys = np.concatenate([K0, K1])
+    got = gpu_answer(pirmod, keys, T.cuda())
+    Tn = T.numpy().view(np.uint32)
+    want = O.answer_batch(keys, Tn, nthreads=cpu_threads())
+    assert (got == want).all()
+
+
+@pytest.mark.parametrize("log_rows,dim,nkeys", [(20, 64, 1), (24, 32, 1), (22, 32, 2), (20, 32, 5)])
+def test_small_batches_sparse_full_size(O, pirmod, log_rows, dim, nkeys):
+    """Single keys and small batches at full domain sizes, per server, on a
+    sparse table of the full shape (oracle by point evaluation)."""
+    import torch
+
+    rows, seed = 1 << log_rows, log_rows + nkeys
+    Ts, sup, vals = make_sparse(rows, dim, seed, 16, "cuda")
+    alphas = W.uniform_indices(rows, nkeys, seed)
+    alphas[0] = sup[3]  # one query hits a non-zero row
+    K0, K1 = oracle_keys(O, log_rows, alphas, seed)
+    keys = np.concatenate([K0, K1])[:nkeys]
+    got = gpu_answer(pirmod, keys, Ts)
+    assert (got == sparse_answers(O, keys, sup, vals)).all()
+    del Ts
+    torch.cuda.empty_cache()
