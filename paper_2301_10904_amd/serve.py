@@ -5,7 +5,8 @@ The tables stay resident in HBM.  A table is admitted only while the resident
 total stays within an HBM budget; a request is admitted only while its
 table's queue is below a bound (beyond it the server is overloaded and the
 request is rejected).  A batch takes up to `max_batch` queued requests of every
-table, copies their keys (already in pinned host memory, as if just received)
+table (fewer for large tables, so that a batch holds at most about
+`max_batch_leaves` leaves of work), copies their keys (already in pinned host memory, as if just received)
 to the device, runs the answer and copies the answers back, all on one side
 stream; several batches may be in flight.  Completion is observed by polling
 HIP events, and the latency of a request is completion time minus arrival
@@ -52,7 +53,7 @@ class PirServer:
     """Resident tables plus a batching request loop on one GPU stream."""
 
     def __init__(self, hbm_budget_bytes: int, max_batch: int = 1024, max_queue: int = 4096,
-                 max_inflight: int = 3, device="cuda:0"):
+                 max_inflight: int = 3, max_batch_leaves: int = 1 << 30, device="cuda:0"):
         import torch
 
         self.torch = torch
@@ -61,6 +62,10 @@ class PirServer:
         self.max_batch = int(max_batch)
         self.max_queue = int(max_queue)
         self.max_inflight = int(max_inflight)
+        # work cap of one batch, in leaves (keys x table rows): keys of large
+        # tables enter in slices so a batch stays short and small tables keep
+        # flowing under overload
+        self.max_batch_leaves = int(max_batch_leaves)
         self.tables = []  # (tensor, rows, dim, n)
         self.resident_bytes = 0
         self.stream = torch.cuda.Stream(device=self.device)
@@ -155,7 +160,8 @@ class PirServer:
                 slot = slots[s]
                 parts, counts = [], []
                 for t in range(T):
-                    take = min(q_len[t], self.max_batch)
+                    by_work = max(16, (self.max_batch_leaves >> self.tables[t][3]) // 16 * 16)
+                    take = min(q_len[t], self.max_batch, by_work)
                     counts.append(take)
                     if take:
                         idx = (q_head[t] + np.arange(take)) % self.max_queue
