@@ -30,19 +30,20 @@ PAPER_V100_QPS = 965.0  # Table 5, AES-128 row, same table shape and batch (cont
 # Algorithmic work of the fused kernel, per internal node of the DPF tree
 # (AES-128 key expansion + two counter blocks, T-table formulation with one
 # v_perm per table address, three-input XORs and the TE/TE8 table pair):
-#   key expansion, per round: 4 addresses + 2 byte selects + 1 xor3 + 1 rcon + 3 xor = 11
-#   round-key rotations for rounds 1..9: 4 per round
+#   key expansion, per round: 4 addresses + 2 byte selects + 1 xor3 + 1 rcon + 3 xor = 11,
+#     run on 16-bit-rotated words (the form the rounds consume): 4 rotations in,
+#     4 out for the last round (1 when only word 0 is needed)
 #   middle round, per column: 4 addresses + 2 xor3 + 1 rotation = 7
 #   last round, per column: 4 addresses + 2 byte selects + 1 xor3 = 7
 #   block 1 shares 3 of the 4 columns of round 1 with block 0
-#   full node  : 110 + 36 + 9*28 + (9*28 - 21) + 2*28 + 8 codeword xors + 1 = 694 VALU ops
+#   full node  : 110 + 8 + 9*28 + (9*28 - 21) + 2*28 + 8 codeword xors + 1 = 666 VALU ops
 #   bottom node (children are leaves, only bytes 0..3 needed):
-#                107 + 36 + 252 + 231 + 2*7 + 2 + 1                          = 643 VALU ops
+#                107 + 5 + 252 + 231 + 2*7 + 2 + 1                           = 612 VALU ops
 #   LDS table lookups: full node 40 + 160 + 148 = 348, bottom node 348 - 24 = 324
 # The share x table product of the batched kernel runs on the int8 matrix
 # cores, so the VALU figure counts the tree alone; the single-query kernel
 # does the product on the VALU (dim x (multiply + add) per leaf).
-VALU_FULL_NODE, VALU_BOTTOM_NODE = 694, 643
+VALU_FULL_NODE, VALU_BOTTOM_NODE = 666, 612
 LOOKUPS_FULL_NODE, LOOKUPS_BOTTOM_NODE = 348, 324
 PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x VALU lanes per clock x clock: 39.3 T int32 op/s
 PEAK_LDS_LOOKUPS = 256 * 32 * 2.4e9  # CUs x 128 B/clk of LDS reads / 4 B: 19.7 T lookups/s

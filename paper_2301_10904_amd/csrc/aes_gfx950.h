@@ -62,7 +62,7 @@ __device__ __forceinline__ uint32_t rot16(uint32_t x) { return __builtin_amdgcn_
 __device__ __forceinline__ uint32_t pick01(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_perm(hi, lo, 0x0c0c0501u); }
 __device__ __forceinline__ uint32_t pick23(uint32_t hi, uint32_t lo) { return __builtin_amdgcn_perm(hi, lo, 0x05010c0cu); }
 
-// One MixColumns output column; kr = rotr16 of the round-key word.
+// One MixColumns output column; kr = rotl16 (= rotr16) of the round-key word.
 __device__ __forceinline__ uint32_t mcol(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t kr, const Lanes &L)
 {
     uint32_t u = xor3(te<2>(c, L), te8<3>(d, L), kr);
@@ -98,21 +98,23 @@ __device__ __forceinline__ void full_round(uint32_t s[4], const uint32_t kr[4], 
 }
 
 // Rounds 1..9 of AES-128 on the counter blocks 0 (state a) and 1 (state b)
-// under key k; on return k holds round key 9.  Block 1 differs from block 0
-// only in byte 15 (row 3 of column 3), which after round 1 affects column 0
-// alone, so round 1 of block 1 reuses columns 1..3 of block 0.
-__device__ __forceinline__ void rounds_1_to_9(uint32_t k[4], uint32_t a[4], uint32_t b[4], const Lanes &L)
+// under key s.  The key schedule runs on rotated words kr = rotl16(k): the
+// schedule commutes with a 16-bit rotation (SubWord and RotWord act on bytes,
+// the rest is XOR), so with Rcon moved to byte 2 the same next_key() yields
+// rotl16 of every round key, which is what mcol() consumes.  On return kr
+// holds rotl16 of round key 9.  Block 1 differs from block 0 only in byte 15
+// (row 3 of column 3), which after round 1 affects column 0 alone, so round 1
+// of block 1 reuses columns 1..3 of block 0.
+__device__ __forceinline__ void rounds_1_to_9(const uint32_t s[4], uint32_t kr[4], uint32_t a[4], uint32_t b[4],
+                                              const Lanes &L)
 {
-    uint32_t kr[4];
-    a[0] = k[0];
-    a[1] = k[1];
-    a[2] = k[2];
-    a[3] = k[3];
-    const uint32_t b3 = k[3] ^ 0x01000000u;
-    next_key(k, pir_aes::RCON.v[1], L);
 #pragma unroll
-    for (int c = 0; c < 4; c++)
-        kr[c] = rot16(k[c]);
+    for (int c = 0; c < 4; c++) {
+        a[c] = s[c];
+        kr[c] = rot16(s[c]);
+    }
+    const uint32_t b3 = s[3] ^ 0x01000000u;
+    next_key(kr, pir_aes::RCON.v[1] << 16, L);
     {
         uint32_t t0 = mcol(a[0], a[1], a[2], a[3], kr[0], L);
         uint32_t u0 = mcol(a[0], a[1], a[2], b3, kr[0], L);
@@ -130,10 +132,7 @@ __device__ __forceinline__ void rounds_1_to_9(uint32_t k[4], uint32_t a[4], uint
     }
 #pragma unroll
     for (int r = 2; r <= 9; r++) {
-        next_key(k, pir_aes::RCON.v[r], L);
-#pragma unroll
-        for (int c = 0; c < 4; c++)
-            kr[c] = rot16(k[c]);
+        next_key(kr, pir_aes::RCON.v[r] << 16, L);
         full_round(a, kr, L);
         full_round(b, kr, L);
     }
@@ -142,13 +141,14 @@ __device__ __forceinline__ void rounds_1_to_9(uint32_t k[4], uint32_t a[4], uint
 // PRF_s(0), PRF_s(1) in full.
 __device__ __forceinline__ void prf_pair(const uint32_t s[4], uint32_t a[4], uint32_t b[4], const Lanes &L)
 {
-    uint32_t k[4] = {s[0], s[1], s[2], s[3]};
-    rounds_1_to_9(k, a, b, L);
-    next_key(k, pir_aes::RCON.v[10], L);
-    uint32_t a0 = fcol(a[0], a[1], a[2], a[3], k[0], L), a1 = fcol(a[1], a[2], a[3], a[0], k[1], L);
-    uint32_t a2 = fcol(a[2], a[3], a[0], a[1], k[2], L), a3 = fcol(a[3], a[0], a[1], a[2], k[3], L);
-    uint32_t b0 = fcol(b[0], b[1], b[2], b[3], k[0], L), b1 = fcol(b[1], b[2], b[3], b[0], k[1], L);
-    uint32_t b2 = fcol(b[2], b[3], b[0], b[1], k[2], L), b3 = fcol(b[3], b[0], b[1], b[2], k[3], L);
+    uint32_t kr[4];
+    rounds_1_to_9(s, kr, a, b, L);
+    next_key(kr, pir_aes::RCON.v[10] << 16, L);
+    const uint32_t k0 = rot16(kr[0]), k1 = rot16(kr[1]), k2 = rot16(kr[2]), k3 = rot16(kr[3]);
+    uint32_t a0 = fcol(a[0], a[1], a[2], a[3], k0, L), a1 = fcol(a[1], a[2], a[3], a[0], k1, L);
+    uint32_t a2 = fcol(a[2], a[3], a[0], a[1], k2, L), a3 = fcol(a[3], a[0], a[1], a[2], k3, L);
+    uint32_t b0 = fcol(b[0], b[1], b[2], b[3], k0, L), b1 = fcol(b[1], b[2], b[3], b[0], k1, L);
+    uint32_t b2 = fcol(b[2], b[3], b[0], b[1], k2, L), b3 = fcol(b[3], b[0], b[1], b[2], k3, L);
     a[0] = a0;
     a[1] = a1;
     a[2] = a2;
@@ -162,22 +162,22 @@ __device__ __forceinline__ void prf_pair(const uint32_t s[4], uint32_t a[4], uin
 // PRF_s(c) alone, for a walk down one path (one block instead of two).
 __device__ __forceinline__ void prf_one(const uint32_t s[4], uint32_t c, uint32_t a[4], const Lanes &L)
 {
-    uint32_t k[4] = {s[0], s[1], s[2], s[3]}, kr[4];
-    a[0] = k[0];
-    a[1] = k[1];
-    a[2] = k[2];
-    a[3] = k[3] ^ (c << 24); // counter block c: byte 15 = c
+    uint32_t kr[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) {
+        a[j] = s[j];
+        kr[j] = rot16(s[j]);
+    }
+    a[3] ^= c << 24; // counter block c: byte 15 = c
 #pragma unroll
     for (int r = 1; r <= 9; r++) {
-        next_key(k, pir_aes::RCON.v[r], L);
-#pragma unroll
-        for (int j = 0; j < 4; j++)
-            kr[j] = rot16(k[j]);
+        next_key(kr, pir_aes::RCON.v[r] << 16, L);
         full_round(a, kr, L);
     }
-    next_key(k, pir_aes::RCON.v[10], L);
-    uint32_t a0 = fcol(a[0], a[1], a[2], a[3], k[0], L), a1 = fcol(a[1], a[2], a[3], a[0], k[1], L);
-    uint32_t a2 = fcol(a[2], a[3], a[0], a[1], k[2], L), a3 = fcol(a[3], a[0], a[1], a[2], k[3], L);
+    next_key(kr, pir_aes::RCON.v[10] << 16, L);
+    const uint32_t k0 = rot16(kr[0]), k1 = rot16(kr[1]), k2 = rot16(kr[2]), k3 = rot16(kr[3]);
+    uint32_t a0 = fcol(a[0], a[1], a[2], a[3], k0, L), a1 = fcol(a[1], a[2], a[3], a[0], k1, L);
+    uint32_t a2 = fcol(a[2], a[3], a[0], a[1], k2, L), a3 = fcol(a[3], a[0], a[1], a[2], k3, L);
     a[0] = a0;
     a[1] = a1;
     a[2] = a2;
@@ -187,11 +187,11 @@ __device__ __forceinline__ void prf_one(const uint32_t s[4], uint32_t c, uint32_
 // Only word 0 (bytes 0..3) of PRF_s(0) and PRF_s(1): what a leaf share uses.
 __device__ __forceinline__ void prf_pair_word0(const uint32_t s[4], uint32_t &y0, uint32_t &y1, const Lanes &L)
 {
-    uint32_t k[4] = {s[0], s[1], s[2], s[3]}, a[4], b[4];
-    rounds_1_to_9(k, a, b, L);
-    const uint32_t w = k[3];
-    const uint32_t k0 = xor3(pick01(te<2>(w, L), te<1>(w, L)), pick23(te<0>(w, L), te<3>(w, L)),
-                             k[0] ^ pir_aes::RCON.v[10]);
+    uint32_t kr[4], a[4], b[4];
+    rounds_1_to_9(s, kr, a, b, L);
+    const uint32_t w = kr[3];
+    const uint32_t k0 = rot16(xor3(pick01(te<2>(w, L), te<1>(w, L)), pick23(te<0>(w, L), te<3>(w, L)),
+                                   kr[0] ^ (pir_aes::RCON.v[10] << 16)));
     y0 = fcol(a[0], a[1], a[2], a[3], k0, L);
     y1 = fcol(b[0], b[1], b[2], b[3], k0, L);
 }
