@@ -5,8 +5,9 @@ CPU-baseline leg of ``bench.py`` may import this package.  The product path
 (the HIP library and its Python binding) shares no code with it.
 
 The arithmetic lives in plain C (``aes_ref.c``: FIPS-197 AES-128;
-``dpf_ref.c``: Gen, the Eq. (p1)-(p3) node recurrence of paper section 3.1,
-the answer T x Eval mod 2^32 and the client's reconstruction).  This module
+``chacha_ref.c``: RFC 8439 ChaCha20; ``dpf_ref.c``: Gen, the Eq. (p1)-(p3)
+node recurrence of paper section 3.1 with either PRF, the answer T x Eval
+mod 2^32 and the client's reconstruction).  This module
 only builds that library with gcc and marshals numpy arrays through ctypes.
 """
 from __future__ import annotations
@@ -19,7 +20,7 @@ from pathlib import Path
 import numpy as np
 
 HERE = Path(__file__).resolve().parent
-SOURCES = ("aes_ref.c", "dpf_ref.c")
+SOURCES = ("aes_ref.c", "chacha_ref.c", "dpf_ref.c")
 LIB_PATH = HERE / "liboracle.so"
 
 _lib = None
@@ -43,10 +44,16 @@ def _bind(lib):
         "or_aes128_expand": (None, [u8p, u8p]),
         "or_aes128": (None, [u8p, u8p, u8p]),
         "or_prf": (None, [u8p, ctypes.c_uint64, u8p]),
+        "or_prf_chacha": (None, [u8p, ctypes.c_uint64, u8p]),
+        "or_prf_by": (ctypes.c_int, [ctypes.c_uint32, u8p, ctypes.c_uint64, u8p]),
+        "or_chacha20_quarter": (None, [u32p, u32p, u32p, u32p]),
+        "or_chacha20_block": (None, [u8p, ctypes.c_uint32, u8p, u8p]),
         "or_drbg_block": (None, [u8p, ctypes.c_uint64, u8p]),
         "or_key_size": (ctypes.c_size_t, [ctypes.c_uint32]),
         "or_gen": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
                                   u8p, u8p, u8p]),
+        "or_gen_prf": (ctypes.c_int, [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                                      u8p, ctypes.c_uint32, u8p, u8p]),
         "or_eval_point": (ctypes.c_uint32, [u8p, ctypes.c_uint64]),
         "or_eval_level": (ctypes.c_int, [u8p, ctypes.c_uint32, u8p]),
         "or_eval_full": (ctypes.c_int, [u8p, u32p]),
@@ -119,6 +126,33 @@ class Oracle:
         self.lib.or_prf(_u8(k), x, _u8(o))
         return o.tobytes()
 
+    def prf_chacha(self, s: bytes, x: int) -> bytes:
+        k = np.frombuffer(bytes(s), np.uint8).copy()
+        o = np.zeros(16, np.uint8)
+        self.lib.or_prf_chacha(_u8(k), x, _u8(o))
+        return o.tobytes()
+
+    def prf_by(self, prf_id: int, s: bytes, x: int) -> bytes:
+        k = np.frombuffer(bytes(s), np.uint8).copy()
+        o = np.zeros(16, np.uint8)
+        if self.lib.or_prf_by(prf_id, _u8(k), x, _u8(o)):
+            raise ValueError("unknown prf id")
+        return o.tobytes()
+
+    # --- ChaCha20 (RFC 8439) ----------------------------------------------------
+    def chacha20_quarter(self, a: int, b: int, c: int, d: int):
+        v = [ctypes.c_uint32(a), ctypes.c_uint32(b), ctypes.c_uint32(c), ctypes.c_uint32(d)]
+        self.lib.or_chacha20_quarter(*[ctypes.pointer(x) for x in v])
+        return tuple(int(x.value) for x in v)
+
+    def chacha20_block(self, key: bytes, counter: int, nonce: bytes) -> bytes:
+        k = np.frombuffer(bytes(key), np.uint8).copy()
+        nc = np.frombuffer(bytes(nonce), np.uint8).copy()
+        assert k.size == 32 and nc.size == 12
+        o = np.zeros(64, np.uint8)
+        self.lib.or_chacha20_block(_u8(k), counter, _u8(nc), _u8(o))
+        return o.tobytes()
+
     def drbg(self, seed: bytes, i: int) -> bytes:
         k = np.frombuffer(bytes(seed), np.uint8).copy()
         o = np.zeros(16, np.uint8)
@@ -129,24 +163,25 @@ class Oracle:
     def key_size(self, n: int) -> int:
         return int(self.lib.or_key_size(n))
 
-    def gen(self, n: int, alpha: int, beta: int, seed: bytes):
+    def gen(self, n: int, alpha: int, beta: int, seed: bytes, prf_id: int = 0):
         """Return (key0, key1) as uint8 arrays, or raise ValueError."""
         ks = self.key_size(n)
         k0 = np.zeros(ks, np.uint8)
         k1 = np.zeros(ks, np.uint8)
         sd = np.frombuffer(bytes(seed), np.uint8).copy()
-        if self.lib.or_gen(n, alpha, beta & 0xFFFFFFFF, _u8(sd), _u8(k0), _u8(k1)):
+        if self.lib.or_gen_prf(n, alpha, beta & 0xFFFFFFFF, _u8(sd), prf_id, _u8(k0),
+                               _u8(k1)):
             raise ValueError("or_gen rejected its arguments")
         return k0, k1
 
-    def gen_batch(self, n: int, alphas, seeds, beta: int = 1):
+    def gen_batch(self, n: int, alphas, seeds, beta: int = 1, prf_id: int = 0):
         """Keys for a batch: returns (keys0, keys1), each [B, key_size] uint8."""
         ks = self.key_size(n)
         B = len(alphas)
         k0 = np.zeros((B, ks), np.uint8)
         k1 = np.zeros((B, ks), np.uint8)
         for q in range(B):
-            a, b = self.gen(n, int(alphas[q]), beta, bytes(seeds[q]))
+            a, b = self.gen(n, int(alphas[q]), beta, bytes(seeds[q]), prf_id)
             k0[q] = a
             k1[q] = b
         return k0, k1

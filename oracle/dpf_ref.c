@@ -14,7 +14,9 @@
  *     in Z_{2^32}.
  *   - "P mod 2" is bit 0 of byte 0 of the seed.
  *   - PRF_s(x) is AES-128 in counter mode: block x of the keystream under key
- *     s, i.e. AES_s(BE128(x)).
+ *     s, i.e. AES_s(BE128(x)).  With prf id 1 (ChaCha20, the stream cipher of
+ *     section 3.2.6) it is bytes [16x, 16x+16) of the RFC 8439 keystream under
+ *     the 256-bit key s || s, nonce zero, block counter from zero.
  *   - Index bits are consumed most significant first (the parent of (d, j)
  *     is (d-1, floor(j/2)), as in the L = 4 walk-through).
  *   - The root sits in the key beside the codewords; the two keys share
@@ -55,6 +57,28 @@ void or_prf(const uint8_t s[16], uint64_t x, uint8_t out[16])
     n_prf_calls++;
 }
 
+/* ChaCha20 keystream bytes [16x, 16x+16) under the key s || s */
+void or_prf_chacha(const uint8_t s[16], uint64_t x, uint8_t out[16])
+{
+    uint8_t key[32], nonce[12] = {0}, blk[64];
+    memcpy(key, s, 16);
+    memcpy(key + 16, s, 16);
+    or_chacha20_block(key, (uint32_t)(x / 4), nonce, blk);
+    memcpy(out, blk + 16 * (x % 4), 16);
+    n_prf_calls++;
+}
+
+int or_prf_by(uint32_t prf_id, const uint8_t s[16], uint64_t x, uint8_t out[16])
+{
+    if (prf_id == OR_PRF_AES128)
+        or_prf(s, x, out);
+    else if (prf_id == OR_PRF_CHACHA20)
+        or_prf_chacha(s, x, out);
+    else
+        return -1;
+    return 0;
+}
+
 void or_drbg_block(const uint8_t seed[16], uint64_t i, uint8_t out[16])
 {
     uint8_t blk[16];
@@ -89,7 +113,7 @@ static const uint8_t *cw(const uint8_t *key, int t, int c, uint32_t d)
 static int key_ok(const uint8_t *key)
 {
     return key && key[0] == 1 && key[1] <= 1 && key[2] >= 1 && key[2] <= 32 &&
-           key[3] == 0;
+           key[3] <= OR_PRF_CHACHA20;
 }
 
 static uint32_t share_of(const uint8_t *key, const uint8_t leaf[16])
@@ -103,14 +127,20 @@ static void child(const uint8_t *key, const uint8_t parent[16], int c, uint32_t 
                   uint8_t out[16])
 {
     uint8_t p[16];
-    or_prf(parent, (uint64_t)c, p);
+    or_prf_by(key[3], parent, (uint64_t)c, p);
     xor16(out, p, cw(key, tbit(parent), c, d));
 }
 
 int or_gen(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t seed[16],
            uint8_t *key0, uint8_t *key1)
 {
-    if (!seed || !key0 || !key1 || n < 1 || n > 32)
+    return or_gen_prf(n, alpha, beta, seed, OR_PRF_AES128, key0, key1);
+}
+
+int or_gen_prf(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t seed[16],
+               uint32_t prf_id, uint8_t *key0, uint8_t *key1)
+{
+    if (!seed || !key0 || !key1 || n < 1 || n > 32 || prf_id > OR_PRF_CHACHA20)
         return -1;
     if (n < 64 && alpha >= ((uint64_t)1 << n))
         return -1;
@@ -128,7 +158,7 @@ int or_gen(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t seed[16],
         keys[b][0] = 1;
         keys[b][1] = (uint8_t)b;
         keys[b][2] = (uint8_t)n;
-        keys[b][3] = 0;
+        keys[b][3] = (uint8_t)prf_id;
         memcpy(keys[b] + 16, s[b], 16);
     }
 
@@ -139,7 +169,7 @@ int or_gen(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t seed[16],
         uint8_t P[2][2][16];                   /* P[b][x] = PRF_{s_b}(x) */
         for (int b = 0; b < 2; b++)
             for (int x = 0; x < 2; x++)
-                or_prf(s[b], (uint64_t)x, P[b][x]);
+                or_prf_by(prf_id, s[b], (uint64_t)x, P[b][x]);
 
         uint8_t C[2][2][16]; /* C[t][c] at this depth */
 

@@ -19,8 +19,12 @@
  *   - Gen(1^lambda, alpha): the paper defers key generation to its DPF
  *     reference; this oracle uses the construction written out in dpf_ref.c.
  *
+ *   - ChaCha20 (RFC 8439) as the alternative PRF of section 3.2.6: PRF_s(x)
+ *     is keystream bytes [16x, 16x+16) under key s || s, nonce 0.
+ *
  * Key byte layout (size 32 + 64 n):
- *   [0] version = 1, [1] party b, [2] n, [3] prf id (0 = AES-128),
+ *   [0] version = 1, [1] party b, [2] n, [3] prf id (0 = AES-128,
+ *   1 = ChaCha20),
  *   [4..15] zero, [16..31] root seed P(0,0) of party b,
  *   then for d = 1..n: C_0[0,d], C_0[1,d], C_1[0,d], C_1[1,d] (16 bytes each).
  *   The 64 n codeword bytes equal the key sizes the paper prints (Table 4).
@@ -41,8 +45,21 @@ void or_aes128_expand(const uint8_t key[16], uint8_t w[176]);
 void or_aes128_encrypt(const uint8_t w[176], const uint8_t in[16], uint8_t out[16]);
 void or_aes128(const uint8_t key[16], const uint8_t in[16], uint8_t out[16]);
 
+/* ChaCha20, RFC 8439 sections 2.1 (quarter round) and 2.3 (block function):
+ * 64 keystream bytes for a 256-bit key, 32-bit block counter, 96-bit nonce. */
+void or_chacha20_quarter(uint32_t *a, uint32_t *b, uint32_t *c, uint32_t *d);
+void or_chacha20_block(const uint8_t key[32], uint32_t counter, const uint8_t nonce[12],
+                       uint8_t out[64]);
+
+#define OR_PRF_AES128 0u
+#define OR_PRF_CHACHA20 1u
+
 /* PRF_s(x) = AES-128_s(BE128(x)); one call = one key expansion + one block. */
 void or_prf(const uint8_t s[16], uint64_t x, uint8_t out[16]);
+/* PRF_s(x) = ChaCha20 keystream bytes [16x, 16x+16) under key s || s, nonce 0. */
+void or_prf_chacha(const uint8_t s[16], uint64_t x, uint8_t out[16]);
+/* PRF selected by prf id; returns -1 for an unknown id. */
+int or_prf_by(uint32_t prf_id, const uint8_t s[16], uint64_t x, uint8_t out[16]);
 /* DRBG draw i under a 16-byte seed: AES-128-CTR keystream block i. */
 void or_drbg_block(const uint8_t seed[16], uint64_t i, uint8_t out[16]);
 
@@ -50,6 +67,10 @@ size_t or_key_size(uint32_t n);
 /* Returns 0, or -1 on bad arguments (n outside [1,32], alpha >= 2^n, null). */
 int or_gen(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t seed[16],
            uint8_t *key0, uint8_t *key1);
+/* Same construction with the tree's PRF chosen by prf_id (the random draws
+ * stay AES-128-CTR); or_gen is prf_id 0.  -1 also for an unknown prf_id. */
+int or_gen_prf(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t seed[16],
+               uint32_t prf_id, uint8_t *key0, uint8_t *key1);
 /* Share of one index j (walks root to leaf). */
 uint32_t or_eval_point(const uint8_t *key, uint64_t j);
 /* All 2^d seeds at depth d (16 bytes each), by the recurrence. */

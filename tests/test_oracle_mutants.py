@@ -2,7 +2,8 @@
 
 Each case copies the oracle's C sources, plants one mistake by text
 substitution, builds the copy on the CPU and runs the pin suites
-(test_oracle_aes.py, test_oracle_dpf.py) against it: they must fail.
+(test_oracle_aes.py, test_oracle_dpf.py, test_oracle_chacha.py) against it:
+they must fail.
 """
 import os
 import shutil
@@ -35,6 +36,14 @@ MUTANTS = {
                                       "((P[1][c][0] & 1) ^ tbit(ns0))"),
     "answer_transposed": ("dpf_ref.c", "ans[k] += y[j] * table[j * dim + k];",
                           "ans[k] += y[j] * table[k * rows + j];"),
+    "chacha_rotation_12_as_13": ("chacha_ref.c", "*b = rotl(*b, 12);", "*b = rotl(*b, 13);"),
+    "chacha_no_feed_forward": ("chacha_ref.c", "uint32_t v = x[i] + init[i];", "uint32_t v = x[i];"),
+    "chacha_wrong_diagonal": ("chacha_ref.c", "qr(x, 1, 6, 11, 12);", "qr(x, 1, 6, 11, 15);"),
+    "chacha_nine_double_rounds": ("chacha_ref.c", "for (int i = 0; i < 10; i++) {", "for (int i = 0; i < 9; i++) {"),
+    "chacha_key_not_doubled": ("dpf_ref.c", "memcpy(key + 16, s, 16);", "memset(key + 16, 0, 16);"),
+    "chacha_child_same_half": ("dpf_ref.c", "memcpy(out, blk + 16 * (x % 4), 16);", "memcpy(out, blk, 16);"),
+    "chacha_tree_uses_aes": ("dpf_ref.c", "or_prf_by(key[3], parent, (uint64_t)c, p);",
+                             "or_prf_by(0, parent, (uint64_t)c, p);"),
     "answer_skips_last_row": ("dpf_ref.c", "for (uint64_t j = 0; j < rows; j++)\n        for (uint32_t k",
                               "for (uint64_t j = 0; j + 1 < rows; j++)\n        for (uint32_t k"),
 }
@@ -52,6 +61,7 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     env = dict(os.environ, ORACLE_LIB_PATH=str(lib))
     r = subprocess.run(
         [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-         str(ROOT / "tests" / "test_oracle_aes.py"), str(ROOT / "tests" / "test_oracle_dpf.py")],
+         str(ROOT / "tests" / "test_oracle_aes.py"), str(ROOT / "tests" / "test_oracle_dpf.py"),
+         str(ROOT / "tests" / "test_oracle_chacha.py")],
         env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
