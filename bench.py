@@ -5,6 +5,8 @@ One step = one pir_answer call: 512 key pairs (1024 keys, both servers' keys
 answered on this GPU) over one table of 2^20 rows x 64 uint32 (256 MiB, rows of
 2048 bits), uniform query indices, AES-128 PRF: the workload of the paper's
 PRF comparison (Table 5: 1,048,576 entries, batch 512, lambda = 128).
+`--prf chacha20` runs the same workload with the ChaCha20 PRF (Table 5's
+ChaCha20 row).
 
 Prints one JSON line.  `value` is server-QPS: keys answered per second by this
 GPU, the unit of the paper's per-GPU QPS.  Inputs are resident in HBM before
@@ -25,7 +27,7 @@ ROOT = Path(__file__).resolve().parent
 sys.path.insert(0, str(ROOT))
 
 METRIC = "PIR queries/sec on 1 MI355X (exact) batched vs single-query; p50/p99 ms"
-PAPER_V100_QPS = 965.0  # Table 5, AES-128 row, same table shape and batch (context only)
+PAPER_V100_QPS = {"aes128": 965.0, "chacha20": 3640.0}  # Table 5 rows, same shape and batch (context only)
 
 # Algorithmic work of the fused kernel, per internal node of the DPF tree
 # (AES-128 key expansion + two counter blocks, T-table formulation with one
@@ -43,22 +45,37 @@ PAPER_V100_QPS = 965.0  # Table 5, AES-128 row, same table shape and batch (cont
 # The share x table product of the batched kernel runs on the int8 matrix
 # cores, so the VALU figure counts the tree alone; the single-query kernel
 # does the product on the VALU (dim x (multiply + add) per leaf).
-VALU_FULL_NODE, VALU_BOTTOM_NODE = 666, 612
-LOOKUPS_FULL_NODE, LOOKUPS_BOTTOM_NODE = 348, 324
+#
+# ChaCha20 (key s || s, counter and nonce zero; no tables): 80 quarter rounds of
+# 4 adds, 4 xors and 4 rotations (one v_alignbit each) = 960, less the 4 xors
+# against the zero words in the first round; 8 feed-forward adds for the two
+# output blocks; 8 codeword xors + 1:
+#   full node  : 960 - 4 + 8 + 8 + 1                                        = 973 VALU ops
+#   bottom node: the last diagonal round needs only word 0 (7 ops of its
+#                quarter round) and word 4 (all 12), two quarter rounds drop
+#                (29 ops), the last column round loses 3 ops, 2 + 2 + 1 at the end:
+#                960 - 4 - 29 - 3 + 2 + 2 + 1                               = 929 VALU ops
+VALU_NODE = {"aes128": (666, 612), "chacha20": (973, 929)}
+LOOKUPS_NODE = {"aes128": (348, 324), "chacha20": (0, 0)}
+VALU_FULL_NODE, VALU_BOTTOM_NODE = VALU_NODE["aes128"]
+LOOKUPS_FULL_NODE, LOOKUPS_BOTTOM_NODE = LOOKUPS_NODE["aes128"]
 PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x VALU lanes per clock x clock: 39.3 T int32 op/s
 PEAK_LDS_LOOKUPS = 256 * 32 * 2.4e9  # CUs x 128 B/clk of LDS reads / 4 B: 19.7 T lookups/s
 KERNEL_SOURCES = ["paper_2301_10904_amd/csrc/pir_device.hip", "paper_2301_10904_amd/csrc/aes_gfx950.h",
-                  "paper_2301_10904_amd/csrc/aes_tables.h"]
-TRAFFIC_SUMMARY = ROOT / "profiles" / "k_pir_waves_2p20x64_b1024_traffic.json"
+                  "paper_2301_10904_amd/csrc/aes_tables.h", "paper_2301_10904_amd/csrc/chacha_gfx950.h"]
+TRAFFIC_SUMMARY = {"aes128": ROOT / "profiles" / "k_pir_waves_2p20x64_b1024_traffic.json",
+                   "chacha20": ROOT / "profiles" / "k_pir_waves_chacha20_2p20x64_b1024_traffic.json"}
 
 
-def algorithmic_work(n: int, keys: int, dim: int, valu_product: bool = False):
+def algorithmic_work(n: int, keys: int, dim: int, valu_product: bool = False, prf: str = "aes128"):
     """(VALU ops, LDS lookups) of one launch over a full 2^n-leaf domain."""
     leaves = 1 << n
     bottom = leaves // 2
     full = bottom - 1
-    valu = keys * (full * VALU_FULL_NODE + bottom * VALU_BOTTOM_NODE + (leaves * 2 * dim if valu_product else 0))
-    lds = keys * (full * LOOKUPS_FULL_NODE + bottom * LOOKUPS_BOTTOM_NODE)
+    vf, vb = VALU_NODE[prf]
+    lf, lb = LOOKUPS_NODE[prf]
+    valu = keys * (full * vf + bottom * vb + (leaves * 2 * dim if valu_product else 0))
+    lds = keys * (full * lf + bottom * lb)
     return valu, lds
 
 
@@ -71,10 +88,10 @@ def kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
+def measured_traffic(prf: str = "aes128"):
     """HBM bytes per launch from the committed PMC summary, if the kernel is unchanged."""
     try:
-        t = json.loads(TRAFFIC_SUMMARY.read_text())
+        t = json.loads(TRAFFIC_SUMMARY[prf].read_text())
     except (OSError, ValueError):
         return None
     if t.get("kernel_digest") != kernel_digest():
@@ -82,8 +99,8 @@ def measured_traffic():
     return t.get("bytes_per_launch")
 
 
-def pmc_summary(paths, kernel_substr="k_pir_", copy_mib=256):
-    """Summarise rocprofv3 --pmc CSVs: per-dispatch counter values of the fused
+def pmc_summary(paths, kernel_substr="k_pir_waves", copy_mib=256):
+    """Summarise rocprofv3 --pmc CSVs: per-dispatch counter values of the batched
     kernel, and FETCH/WRITE scale factors from the plain copy of copy_mib MiB."""
     import csv
     import collections
@@ -93,7 +110,7 @@ def pmc_summary(paths, kernel_substr="k_pir_", copy_mib=256):
     for p in paths:
         for r in csv.DictReader(open(p)):
             name, cn, v = r["Kernel_Name"], r["Counter_Name"], float(r["Counter_Value"])
-            if kernel_substr in name and "<1," not in name:
+            if kernel_substr in name:
                 per[(p, r["Dispatch_Id"])][cn] = per[(p, r["Dispatch_Id"])].get(cn, 0.0) + v
             elif "copyBuffer" in name:
                 copy[(p, r["Dispatch_Id"], cn)].append(v)
@@ -143,12 +160,15 @@ def main():
     ap.add_argument("--dim", type=int, default=64)
     ap.add_argument("--seed", type=int, default=2)
     ap.add_argument("--single-steps", type=int, default=50)
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=64,
+                    help="keys of the workload the oracle answers for the CPU baseline (x8 for ChaCha20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="batch", choices=["batch", "small", "multi", "large", "serve"],
                     help="batch: 2^20 x 64, 512 pairs (the default line); small: 2^14 x 16, one pair; "
                          "multi: 8 tables 2^16..2^23 x 32, ragged Zipf batches in one call; "
                          "large: 2^25 x 64 (8 GiB), 512..2048 pairs; serve: Poisson request loop over 4 tables")
+    ap.add_argument("--prf", default="aes128", choices=["aes128", "chacha20"],
+                    help="the DPF tree's PRF (section 3.2.6): AES-128 (default) or ChaCha20")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="summarise rocprofv3 --pmc counter CSVs of this benchmark and exit")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -158,7 +178,8 @@ def main():
 
     if args.pmc_summary:
         avg, scale, dispatches = pmc_summary(args.pmc_summary, copy_mib=args.calibrate_copy or 256)
-        out = {"kernel": "k_pir_waves (the 1024-key launch)", "dispatches": dispatches, "counters_avg": avg,
+        out = {"kernel": f"k_pir_waves (the 1024-key launch, {args.prf})", "prf": args.prf,
+               "dispatches": dispatches, "counters_avg": avg,
                "copy_scale": scale, "kernel_digest": kernel_digest()}
         if "FETCH_SIZE" in avg and "WRITE_SIZE" in avg and len(scale) == 2:
             out["bytes_per_launch"] = int(1024 * (avg["FETCH_SIZE"] * scale["FETCH_SIZE"] +
@@ -185,7 +206,8 @@ def main():
     n = pir.log_domain(rows)
     table = W.make_table(rows, dim, args.seed, device=dev)
     alphas = W.uniform_indices(rows, pairs, args.seed)
-    K0, K1 = pir.gen_batch(n, alphas, W.key_seeds(pairs, args.seed))
+    prf = args.prf
+    K0, K1 = pir.gen_batch(n, alphas, W.key_seeds(pairs, args.seed), prf=prf)
     keys_np = np.concatenate([K0, K1])
     keys = torch.from_numpy(keys_np).to(dev)
     B = keys.shape[0]
@@ -193,7 +215,7 @@ def main():
     torch.cuda.synchronize()
 
     for _ in range(args.warmup):
-        pir.answer(keys, table, out)
+        pir.answer(keys, table, out, prf=prf)
     torch.cuda.synchronize()
 
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -202,7 +224,7 @@ def main():
     t0 = time.perf_counter()
     for e0, e1 in evs:
         e0.record()
-        pir.answer(keys, table, out)
+        pir.answer(keys, table, out, prf=prf)
         e1.record()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -221,14 +243,14 @@ def main():
     k1 = keys[:1].contiguous()
     o1 = torch.empty((1, dim), dtype=torch.int32, device=dev)
     for _ in range(3):
-        pir.answer(k1, table, o1)
+        pir.answer(k1, table, o1, prf=prf)
     torch.cuda.synchronize()
     sev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.single_steps)]
     s0 = time.perf_counter()
     for e0, e1 in sev:
         e0.record()
-        pir.answer(k1, table, o1)
+        pir.answer(k1, table, o1, prf=prf)
         e1.record()
     torch.cuda.synchronize()
     s1 = time.perf_counter()
@@ -243,23 +265,24 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    valu_ops, lookups = algorithmic_work(n, B, dim)
+    valu_ops, lookups = algorithmic_work(n, B, dim, prf=prf)
     kern_s = float(np.mean(launch_ms)) / 1e3
     achieved = valu_ops / kern_s / 1e12
     peak = PEAK_INT32_OPS / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(),
+                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(prf),
                 "kernel": "k_pir_waves", "valu_ops_per_launch": valu_ops,
                 "avg_launch_ms": round(kern_s * 1e3, 4), "kernel_digest": kernel_digest()}
     lds_rate = lookups / kern_s / 1e12
     roofline_lds = {"achieved": round(lds_rate, 3), "peak": round(PEAK_LDS_LOOKUPS / 1e12, 3),
                     "unit": "T lookups/s", "frac": round(lds_rate * 1e12 / PEAK_LDS_LOOKUPS, 4),
-                    "lookups_per_launch": lookups}
+                    "lookups_per_launch": lookups} if lookups else None
 
     cpu = None
     if not args.no_cpu_baseline:
         threads = max(1, min(16, os.cpu_count() or 1))
-        cpu = cpu_baseline(keys_np, table.cpu().numpy().view(np.uint32), args.cpu_sample, threads)
+        cpu = cpu_baseline(keys_np, table.cpu().numpy().view(np.uint32),
+                           args.cpu_sample * (8 if prf == "chacha20" else 1), threads)
 
     res = {
         "metric": METRIC,
@@ -271,13 +294,16 @@ def main():
         "ms_per_step": round(ms_per_step, 4),
         "higher_is_better": True,
         "scaling": "weak",
-        "vs_baseline": round(value / PAPER_V100_QPS, 2) if (rows, dim, pairs) == (1 << 20, 64, 512) else None,
-        "vs_baseline_ref": "paper Table 5 AES-128, NVIDIA V100: 965 QPS (context, another GPU)",
+        "vs_baseline": (round(value / PAPER_V100_QPS[prf], 2)
+                        if (rows, dim, pairs) == (1 << 20, 64, 512) else None),
+        "vs_baseline_ref": (f"paper Table 5 {'AES-128' if prf == 'aes128' else 'ChaCha20'}, NVIDIA V100: "
+                            f"{PAPER_V100_QPS[prf]:.0f} QPS (context, another GPU)"),
         "dtype": "u32",
         "data": "synthetic",
         "config": {"workload": f"one table 2^{args.log_rows} rows x {dim} uint32, {pairs} key pairs "
-                               f"= {B} keys per step (both servers), uniform alpha, AES-128 PRF",
-                   "rows": rows, "dim": dim, "keys_per_step": B, "log_domain": n},
+                               f"= {B} keys per step (both servers), uniform alpha, "
+                               f"{'AES-128' if prf == 'aes128' else 'ChaCha20'} PRF",
+                   "rows": rows, "dim": dim, "keys_per_step": B, "log_domain": n, "prf": prf},
         "retrieval_qps": round(value / 2, 2),
         "batched_latency_ms": {"p50": round(percentile(launch_ms, 50), 4),
                                "p99": round(percentile(launch_ms, 99), 4)},
@@ -319,16 +345,17 @@ def other_modes(args):
     from paper_2301_10904_amd import workloads as W
 
     dev = torch.device("cuda:0")
+    prf = args.prf
     line = {"metric": METRIC, "unit": "server queries/s", "n_gpus": 1, "higher_is_better": True,
-            "dtype": "u32", "data": "synthetic", "mode": args.mode}
+            "dtype": "u32", "data": "synthetic", "mode": args.mode, "prf": prf}
     if args.mode == "small":
         rows, dim = 1 << 14, 16
         T = W.make_table(rows, dim, 1, device=dev)
         a = W.uniform_indices(rows, 1, 1)
-        K0, K1 = pir.gen_batch(14, a, W.key_seeds(1, 1))
+        K0, K1 = pir.gen_batch(14, a, W.key_seeds(1, 1), prf=prf)
         keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
         out = torch.empty((2, dim), dtype=torch.int32, device=dev)
-        sec, ms = time_launches(lambda: pir.answer(keys, T, out), 200, 10)
+        sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=prf), 200, 10)
         got = out.cpu().numpy().view(np.uint32)
         ok = bool((pir.reconstruct(got[0], got[1]) == W.table_rows_np(a, dim, 1)[0]).all())
         line.update(value=round(2 / sec, 1), exact=ok, p50_ms=round(percentile(ms, 50), 4),
@@ -342,14 +369,14 @@ def other_modes(args):
             rows = 1 << (16 + t)
             tables.append(W.make_table(rows, 32, seed + t, device=dev))
             a = W.zipf_indices(rows, int(sizes[t]), seed + t)
-            K0, K1 = pir.gen_batch(16 + t, a, W.key_seeds(len(a), seed + t))
+            K0, K1 = pir.gen_batch(16 + t, a, W.key_seeds(len(a), seed + t), prf=prf)
             keys_l.append(np.concatenate([K0, K1]))
             counts.append(2 * int(sizes[t]))
             alphas.append(a)
         stride = (max(k.shape[1] for k in keys_l) + 15) // 16 * 16
         keys = torch.from_numpy(np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keys_l])).to(dev)
-        out, views = pir.answer_multi(tables, counts, keys)
-        sec, ms = time_launches(lambda: pir.answer_multi(tables, counts, keys, out=out), 5, 1)
+        out, views = pir.answer_multi(tables, counts, keys, prf=prf)
+        sec, ms = time_launches(lambda: pir.answer_multi(tables, counts, keys, out=out, prf=prf), 5, 1)
         ok = True
         for t in range(8):
             got = views[t].cpu().numpy().view(np.uint32)
@@ -366,17 +393,17 @@ def other_modes(args):
         res = {}
         for pairs in (512, 1024, 2048):
             a = W.uniform_indices(rows, pairs, seed)
-            K0, K1 = pir.gen_batch(25, a, W.key_seeds(pairs, seed))
+            K0, K1 = pir.gen_batch(25, a, W.key_seeds(pairs, seed), prf=prf)
             keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
             out = torch.empty((2 * pairs, dim), dtype=torch.int32, device=dev)
-            sec, ms = time_launches(lambda: pir.answer(keys, T, out), 2, 1)
+            sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=prf), 2, 1)
             got = out.cpu().numpy().view(np.uint32)
             rec = ((got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF).astype(np.uint32)
             res[2 * pairs] = {"server_qps": round(2 * pairs / sec, 1), "ms": round(sec * 1e3, 2),
                               "exact": bool((rec == W.table_rows_np(a, dim, seed)).all())}
         k1 = keys[:1].contiguous()
         o1 = torch.empty((1, dim), dtype=torch.int32, device=dev)
-        sec1, ms1 = time_launches(lambda: pir.answer(k1, T, o1), 20, 3)
+        sec1, ms1 = time_launches(lambda: pir.answer(k1, T, o1, prf=prf), 20, 3)
         line.update(value=res[4096]["server_qps"], batches=res,
                     single_query={"qps": round(1 / sec1, 1), "p50_ms": round(percentile(ms1, 50), 3),
                                   "p99_ms": round(percentile(ms1, 99), 3)},
@@ -397,13 +424,13 @@ def serve_sweep(args):
     dev = torch.device("cuda:0")
     logs = [18, 20, 22, 24]
     srv = PirServer(hbm_budget_bytes=4 << 30, max_batch=1024, max_queue=8192, max_inflight=3,
-                    max_batch_leaves=1 << 29)
+                    max_batch_leaves=1 << 29, prf=args.prf)
     pool, pool_alpha = [], []
     for i, lg in enumerate(logs):
         T = W.make_table(1 << lg, 32, 50 + i, device=dev)
         assert srv.admit_table(T) == i
         a = W.uniform_indices(1 << lg, 512, 50 + i)
-        K0, K1 = pir.gen_batch(lg, a, W.key_seeds(512, 50 + i))
+        K0, K1 = pir.gen_batch(lg, a, W.key_seeds(512, 50 + i), prf=args.prf)
         pool.append(np.concatenate([K0, K1]))
         pool_alpha.append(np.concatenate([a, a]))
     stride = (max(k.shape[1] for k in pool) + 15) // 16 * 16
@@ -414,7 +441,7 @@ def serve_sweep(args):
         # the served share and its partner's share (answered directly) reconstruct T[alpha]
         partner = ki + 512 if ki < 512 else ki - 512
         pk = torch.from_numpy(pool[t][partner:partner + 1]).to(dev)
-        other = pir.answer(pk, srv.tables[t][0]).cpu().numpy().view(np.uint32)[0]
+        other = pir.answer(pk, srv.tables[t][0], prf=args.prf).cpu().numpy().view(np.uint32)[0]
         want = W.table_rows_np([pool_alpha[t][ki]], 32, 50 + t)[0]
         if not (pir.reconstruct(row, other) == want).all():
             bad.append((t, int(ki), int(np.sum(pir.reconstruct(row, other) != want))))

@@ -25,7 +25,7 @@
  *
  * DPF key layout (bytes; dpf_key_size(n) = 32 + 64 n):
  *   [0] version = 1   [1] party b in {0,1}   [2] n = log2 of the domain
- *   [3] PRF id, 0 = AES-128 in counter mode   [4..15] zero
+ *   [3] PRF id: PIR_PRF_AES128 (0) or PIR_PRF_CHACHA20 (1)   [4..15] zero
  *   [16..31] root seed P(0,0) of party b (16 bytes)
  *   [32 + 64 (d-1) + 32 t + 16 c .. +15] codeword C_t[c, d], d = 1..n,
  *                                        t, c in {0,1}
@@ -37,6 +37,10 @@
  *                            XOR C_{t(P(d-1, j/2))}[j mod 2, d]
  *   with t(s) = bit 0 of byte 0 of s; the share of row j is
  *   (-1)^b * (bytes 0..3 of P(n,j) read little-endian) mod 2^32.
+ *   With PRF id 1 the AES block is replaced by the ChaCha20 stream cipher
+ *   the paper also evaluates (section 3.2.6, Table 5): PRF_s(x) is bytes
+ *   [16x, 16x+16) of the RFC 8439 keystream under the 256-bit key s || s,
+ *   nonce 0, block counter 0.
  */
 #ifndef PIR_H
 #define PIR_H
@@ -59,6 +63,10 @@ extern "C" {
 #define PIR_MAX_LOG_DOMAIN 32 /* n <= 32: tables of at most 2^32 rows */
 #define PIR_MAX_DIM 256       /* uint32 columns per row (1 KiB rows)  */
 
+/* PRF ids (key byte 3) */
+#define PIR_PRF_AES128 0u   /* AES-128 of the counter block BE128(x)          */
+#define PIR_PRF_CHACHA20 1u /* ChaCha20 keystream bytes [16x, 16x+16), s || s */
+
 /* Size in bytes of one DPF key over a domain of 2^n indices: 32 + 64 n.
  * Returns 0 for n outside [1, 32]. */
 size_t dpf_key_size(uint32_t n);
@@ -76,6 +84,14 @@ size_t dpf_key_size(uint32_t n);
  * and PIR_EHIP if the operating system refuses randomness. */
 int dpf_gen(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16,
             uint8_t *key0, uint8_t *key1);
+
+/* Gen with the tree's PRF chosen by prf_id (section 3.2.6: the PRF is a free
+ * choice of the construction; PIR_PRF_AES128 or PIR_PRF_CHACHA20).  The
+ * random draws stay the AES-128-CTR keystream under seed16, so two calls with
+ * the same seed and different prf_id share their roots and random codewords.
+ * dpf_gen is prf_id = PIR_PRF_AES128.  PIR_EINVAL also for an unknown prf_id. */
+int dpf_gen_prf(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16,
+                uint32_t prf_id, uint8_t *key0, uint8_t *key1);
 
 /* Server side answer for one table (paper section 3.1: T x Eval(k, {0..L-1});
  * fused evaluation as in sections 3.2.3-3.2.4).
@@ -97,6 +113,14 @@ int pir_answer(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride,
                const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out,
                void *stream);
 
+/* pir_answer for keys of the PRF prf_id (section 3.2.6): every key of the
+ * call must carry prf_id in byte 3, else it is treated as a bad header (zero
+ * output row, flag for pir_check_status).  pir_answer is prf_id =
+ * PIR_PRF_AES128.  PIR_EINVAL also for an unknown prf_id. */
+int pir_answer_prf(uint32_t prf_id, const uint8_t *d_keys, uint32_t n_keys,
+                   uint32_t key_stride, const uint32_t *d_table, uint64_t rows,
+                   uint32_t dim, uint32_t *d_out, void *stream);
+
 /* One table of a multi-table call. */
 typedef struct {
     const uint32_t *d_table; /* row-major uint32 [rows][dim] in HBM */
@@ -117,6 +141,11 @@ typedef struct {
  * Errors as for pir_answer; any bad descriptor rejects the whole call. */
 int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t *d_keys,
                      uint32_t key_stride, uint32_t *d_out, void *stream);
+
+/* pir_answer_multi for keys of the PRF prf_id, as pir_answer_prf. */
+int pir_answer_multi_prf(uint32_t prf_id, const pir_table_t *tables, uint32_t n_tables,
+                         const uint8_t *d_keys, uint32_t key_stride, uint32_t *d_out,
+                         void *stream);
 
 /* Client side reconstruction (paper section 3.1): out[k] = a0[k] + a1[k]
  * mod 2^32 for k < dim; host buffers.  PIR_EINVAL on null pointers. */

@@ -27,6 +27,8 @@
 // AES-128 (aes_gfx950.h) runs on little-endian column words with the combined
 // SubBytes/MixColumns tables replicated per lane in LDS, so table lookups never
 // conflict; the tables fill the first 64 KiB, and two workgroups share a CU.
+// Keys with the ChaCha20 PRF (chacha_gfx950.h, section 3.2.6) run the same
+// kernels instantiated with a register-only PRF and no table in LDS.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -34,6 +36,7 @@
 
 #include "aes_gfx950.h"
 #include "aes_tables.h"
+#include "chacha_gfx950.h"
 #include "pir.h"
 #include "pir_internal.h"
 
@@ -53,9 +56,51 @@ struct Seed {
     uint32_t w[4];
 };
 
-// The whole LDS of a workgroup.
+// The PRF of a launch.  Each provides both children's PRF outputs of a node,
+// one child's, and word 0 of both (all a leaf share needs); TAB_WORDS is the
+// LDS table it reads (filled by fill()), 0 for none.
+struct AesPrf {
+    static constexpr uint32_t id = PIR_PRF_AES128;
+    static constexpr uint32_t TAB_WORDS = AES_TAB_WORDS;
+    Lanes L;
+    __device__ __forceinline__ AesPrf(const uint32_t *tab, uint32_t lane) : L(tab, lane) {}
+    static __device__ __forceinline__ void fill(uint32_t *tab, uint32_t tid, uint32_t nt)
+    {
+        fill_tables(tab, c_TE.v, tid, nt);
+    }
+    __device__ __forceinline__ void pair(const uint32_t s[4], uint32_t a[4], uint32_t b[4]) const
+    {
+        prf_pair(s, a, b, L);
+    }
+    __device__ __forceinline__ void one(const uint32_t s[4], uint32_t c, uint32_t a[4]) const { prf_one(s, c, a, L); }
+    __device__ __forceinline__ void pair_word0(const uint32_t s[4], uint32_t &y0, uint32_t &y1) const
+    {
+        prf_pair_word0(s, y0, y1, L);
+    }
+};
+
+struct ChaChaPrf {
+    static constexpr uint32_t id = PIR_PRF_CHACHA20;
+    static constexpr uint32_t TAB_WORDS = 0;
+    __device__ __forceinline__ ChaChaPrf(const uint32_t *, uint32_t) {}
+    static __device__ __forceinline__ void fill(uint32_t *, uint32_t, uint32_t) {}
+    __device__ __forceinline__ void pair(const uint32_t s[4], uint32_t a[4], uint32_t b[4]) const
+    {
+        chacha_pair(s, a, b);
+    }
+    __device__ __forceinline__ void one(const uint32_t s[4], uint32_t c, uint32_t a[4]) const { chacha_one(s, c, a); }
+    __device__ __forceinline__ void pair_word0(const uint32_t s[4], uint32_t &y0, uint32_t &y1) const
+    {
+        chacha_pair_word0(s, y0, y1);
+    }
+};
+
+// The whole LDS of a workgroup: the PRF's table (if any), which is reused for
+// the cross-wave sums of up to QMAX x PIR_MAX_DIM words.
+template <uint32_t TABW>
 struct Smem {
-    uint32_t tab[AES_TAB_WORDS];   // 64 KiB, later reused for the cross-wave sums
+    static constexpr uint32_t W = TABW > QMAX * PIR_MAX_DIM ? TABW : QMAX * PIR_MAX_DIM;
+    uint32_t tab[W];
     union {
         Seed bfs[NT];              // breadth-first nodes
         uint32_t sh[2 * NT];       // leaf shares of one walk step: [2 S][Q]
@@ -85,24 +130,26 @@ struct KeyView {
 };
 
 // Both children of the node with seed s, codeword level d (Eq. (p3)).
-__device__ __forceinline__ void children(const Lanes &L, const KeyView &K, const Seed &s, uint32_t d, Seed &c0,
+template <class PRF>
+__device__ __forceinline__ void children(const PRF &P, const KeyView &K, const Seed &s, uint32_t d, Seed &c0,
                                          Seed &c1)
 {
     uint4 w0, w1;
     K.cw(d, s.w[0] & 1u, w0, w1);
     uint32_t a[4], b[4];
-    prf_pair(s.w, a, b, L);
+    P.pair(s.w, a, b);
     c0 = Seed{{a[0] ^ w0.x, a[1] ^ w0.y, a[2] ^ w0.z, a[3] ^ w0.w}};
     c1 = Seed{{b[0] ^ w1.x, b[1] ^ w1.y, b[2] ^ w1.z, b[3] ^ w1.w}};
 }
 
 // Child c of the node with seed s, codeword level d (Eq. (p3)), for descents.
-__device__ __forceinline__ Seed child_on_path(const Lanes &L, const KeyView &K, const Seed &s, uint32_t d, uint32_t c)
+template <class PRF>
+__device__ __forceinline__ Seed child_on_path(const PRF &P, const KeyView &K, const Seed &s, uint32_t d, uint32_t c)
 {
     const uint4 *q = reinterpret_cast<const uint4 *>(K.p + 32 + 64 * (size_t)(d - 1) + 32 * (s.w[0] & 1u) + 16 * c);
     const uint4 w = *q;
     uint32_t a[4];
-    prf_one(s.w, c, a, L);
+    P.one(s.w, c, a);
     return Seed{{a[0] ^ w.x, a[1] ^ w.y, a[2] ^ w.z, a[3] ^ w.w}};
 }
 
@@ -124,23 +171,23 @@ struct Geometry {
 
 // Q keys per group (Q <= QMAX); KCH column chunks of 64 (dim <= 64 KCH);
 // VEC4: dim is a multiple of 4 (16-byte row segments are aligned).
-template <int Q, int KCH, bool VEC4>
+template <class PRF, int Q, int KCH, bool VEC4>
 __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ keys, uint32_t n_keys,
                                                   uint32_t stride, const uint32_t *__restrict__ table,
                                                   uint64_t rows, uint32_t dim, uint32_t *__restrict__ out,
                                                   Geometry g)
 {
     constexpr int S = NT / Q;
-    __shared__ Smem sm;
+    __shared__ Smem<PRF::TAB_WORDS> sm;
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63, wave = tid >> 6;
     const uint32_t grp = blockIdx.x % g.n_groups;
     const uint32_t chunk = blockIdx.x / g.n_groups;
     const uint64_t row_base = (uint64_t)chunk << g.H;
-    const Lanes L(sm.tab, lane);
+    const PRF P(sm.tab, lane);
 
-    fill_tables(sm.tab, c_TE.v, tid, NT);
+    PRF::fill(sm.tab, tid, NT);
 
     // key headers; roots of the keys
     const uint32_t dtop = g.n - g.H;
@@ -152,7 +199,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             const KeyView K{keys + (size_t)kq * stride};
             const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
             const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
-            ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == 0) ? 1u + party : 0u;
+            ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == PRF::id) ? 1u + party : 0u;
             if (!ok)
                 atomicOr(&g_key_error, 1u);
             else
@@ -168,7 +215,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         const KeyView K{keys + (size_t)(grp * Q + tid) * stride};
         Seed s = sm.u.bfs[tid];
         for (uint32_t d = 1; d <= dtop; d++)
-            s = child_on_path(L, K, s, d, (uint32_t)(row_base >> (g.n - d)) & 1u);
+            s = child_on_path(P, K, s, d, (uint32_t)(row_base >> (g.n - d)) & 1u);
         sm.u.bfs[tid] = s;
     }
     __syncthreads();
@@ -181,7 +228,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         Seed c0{{0, 0, 0, 0}}, c1{{0, 0, 0, 0}};
         if (mine && sm.keyok[q]) {
             const KeyView K{keys + (size_t)(grp * Q + q) * stride};
-            children(L, K, sm.u.bfs[tid], dtop + l, c0, c1);
+            children(P, K, sm.u.bfs[tid], dtop + l, c0, c1);
         }
         __syncthreads(); // every parent has been read
         if (mine) {
@@ -242,7 +289,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         if (active) {
             for (uint32_t k = kst; k < h; k++) {
                 Seed c0, c1;
-                children(L, K, node, d0 + k, c0, c1);
+                children(P, K, node, d0 + k, c0, c1);
 #pragma unroll
                 for (int i = 1; i < HMAX; i++)
                     if ((uint32_t)i == k)
@@ -250,7 +297,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
                 node = c0;
             }
             const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
-            prf_pair_word0(node.w, y0, y1, L);
+            P.pair_word0(node.w, y0, y1);
             y0 ^= cw.x;
             y1 ^= cw.y;
         }
@@ -401,8 +448,8 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
 // of (x + 0x80808080) ^ 0x80808080.  Then
 //     y * T = sum_{s=0..3} 256^s * sum_{a+b=s} d_a(y) e_b(T)      (mod 2^32),
 // so for each s one MFMA with A = digits of y arranged d_s, d_{s-1}, .., d_0
-// and B = digits of T gives the s-th term; the int32 accumulators wrap mod 2^32
-// and the four are combined with shifts at the end.
+// and B = digits of T gives the s-th term; the int32 accumulators wrap mod 2^32.
+// Each step folds its four terms into one running sum per tile.
 // ---------------------------------------------------------------------------
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -473,15 +520,17 @@ struct WaveTasks {
     uint32_t count, n_items;
 };
 
-template <int KT, bool VEC>
+template <class PRF, int KT, bool VEC>
 __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_waves(const WaveTasks tasks,
                                                                                            uint32_t stride)
 {
-    __shared__ uint32_t tab[AES_TAB_WORDS];
+    __shared__ uint32_t tab[PRF::TAB_WORDS ? PRF::TAB_WORDS : 1];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const Lanes L(tab, lane);
-    fill_tables(tab, c_TE.v, tid, NT3);
-    __syncthreads();
+    const PRF P(tab, lane);
+    if (PRF::TAB_WORDS) {
+        PRF::fill(tab, tid, NT3);
+        __syncthreads();
+    }
 
     const uint32_t item0 = blockIdx.x * NW3 + wave;
     if (item0 >= tasks.n_items)
@@ -506,7 +555,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (kq < n_keys) {
         const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
         const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
-        ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == 0) ? 1u + party : 0u;
+        ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == PRF::id) ? 1u + party : 0u;
         if (!ok && sub == 0)
             atomicOr(&g_key_error, 1u);
     }
@@ -518,7 +567,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (active) {
         node = K.root();
         for (uint32_t d = 1; d + h <= g.n; d++)
-            node = child_on_path(L, K, node, d, (uint32_t)(lane_row0 >> (g.n - d)) & 1u);
+            node = child_on_path(P, K, node, d, (uint32_t)(lane_row0 >> (g.n - d)) & 1u);
     }
     const uint32_t d0 = g.n - h;
     Seed right[HMAX3];
@@ -557,7 +606,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
         if (active) {
             for (uint32_t k = kst; k < h; k++) {
                 Seed c0, c1;
-                children(L, K, node, d0 + k, c0, c1);
+                children(P, K, node, d0 + k, c0, c1);
 #pragma unroll
                 for (int i = 1; i < HMAX3; i++)
                     if ((uint32_t)i == k)
@@ -565,7 +614,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
                 node = c0;
             }
             const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
-            prf_pair_word0(node.w, y0, y1, L);
+            P.pair_word0(node.w, y0, y1);
             y0 ^= cw.x;
             y1 ^= cw.y;
         }
@@ -578,15 +627,24 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
         const v4i zero = {0, 0, 0, 0};
 #pragma unroll
         for (int t = 0; t < KT; t++) {
+            // tot += D_0 + 2^8 (D_1 + 2^8 (D_2 + 2^8 D_3)): D_0 accumulates in
+            // the matrix core, the rest is three shift-and-add steps per word
             const long b = pack2(balanced(t0[t]), balanced(t1[t]));
-            const v4i c0 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b, zero, 0, 0, 0);
             const v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b, zero, 0, 0, 0);
             const v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a2, b, zero, 0, 0, 0);
             const v4i c3 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3, b, zero, 0, 0, 0);
+            v4i acc = tot[t];
 #pragma unroll
-            for (int i = 0; i < 4; i++)
-                tot[t][i] = (int)((uint32_t)tot[t][i] + (uint32_t)c0[i] + ((uint32_t)c1[i] << 8) +
-                                  ((uint32_t)c2[i] << 16) + ((uint32_t)c3[i] << 24));
+            for (int i = 0; i < 4; i++) {
+                // the empty asm keeps each (x << 8) + y a single v_lshl_add_u32
+                // (the compiler would otherwise expand the chain into separate shifts)
+                uint32_t hi = ((uint32_t)c3[i] << 8) + (uint32_t)c2[i];
+                asm volatile("" : "+v"(hi));
+                hi = (hi << 8) + (uint32_t)c1[i];
+                asm volatile("" : "+v"(hi));
+                acc[i] = (int)((uint32_t)acc[i] + (hi << 8));
+            }
+            tot[t] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b, acc, 0, 0, 0);
         }
     }
 
@@ -618,13 +676,13 @@ static uint32_t ceil_log2(uint64_t x)
     return r;
 }
 
-template <int Q>
+template <class PRF, int Q>
 static void launch_q(uint32_t kch, dim3 grid, hipStream_t st, const uint8_t *keys, uint32_t n_keys,
                      uint32_t stride, const uint32_t *table, uint64_t rows, uint32_t dim, uint32_t *out,
                      const Geometry &g)
 {
 #define PIR_LAUNCH_FUSED(KCH, V4)                                                                                 \
-    hipLaunchKernelGGL((k_pir_fused<Q, KCH, V4>), grid, dim3(NT), 0, st, keys, n_keys, stride, table, rows, dim, \
+    hipLaunchKernelGGL((k_pir_fused<PRF, Q, KCH, V4>), grid, dim3(NT), 0, st, keys, n_keys, stride, table, rows, dim, \
                        out, g)
     const bool v4 = dim % 4 == 0;
     if (kch == 1) {
@@ -654,6 +712,7 @@ static int fail_hip(hipError_t e)
 
 // Wave-kernel launch for up to MAX_TASKS tables of one column class (KT, VEC).
 // Fills h, n_groups and item_begin of every task; clears the outputs first.
+template <class PRF>
 static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipStream_t st, uint64_t min_items)
 {
     WaveTasks W;
@@ -685,7 +744,7 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipSt
         return PIR_OK;
     const dim3 grid((uint32_t)((items + NW3 - 1) / NW3));
     const uint32_t dim = ts[0].dim;
-#define PIR_LAUNCH_WAVES(KT, VEC) hipLaunchKernelGGL((k_pir_waves<KT, VEC>), grid, dim3(NT3), 0, st, W, key_stride)
+#define PIR_LAUNCH_WAVES(KT, VEC) hipLaunchKernelGGL((k_pir_waves<PRF, KT, VEC>), grid, dim3(NT3), 0, st, W, key_stride)
     if (dim == 64)
         PIR_LAUNCH_WAVES(4, true);
     else if (dim == 32)
@@ -716,6 +775,7 @@ static int wave_class(uint32_t dim)
 }
 
 // Validates one table's call and enqueues its kernels.
+template <class PRF>
 static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, const uint32_t *d_table,
                       uint64_t rows, uint32_t dim, uint32_t *d_out, hipStream_t st)
 {
@@ -739,7 +799,7 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
         t.dim = dim;
         t.n_keys = n_keys;
         t.n = n;
-        return launch_waves(&t, 1, key_stride, st, 8192);
+        return launch_waves<PRF>(&t, 1, key_stride, st, 8192);
     }
 
     const uint32_t Q = n_keys >= QMAX ? QMAX : (uint32_t)1 << ceil_log2(n_keys);
@@ -766,28 +826,19 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
     hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks), dim3(256), 0, st, d_out, count);
     const dim3 grid((uint32_t)(chunks * groups));
     switch (Q) {
-    case 1: launch_q<1>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
-    case 2: launch_q<2>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
-    case 4: launch_q<4>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
-    case 8: launch_q<8>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
-    default: launch_q<16>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
+    case 1: launch_q<PRF, 1>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
+    case 2: launch_q<PRF, 2>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
+    case 4: launch_q<PRF, 4>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
+    case 8: launch_q<PRF, 8>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
+    default: launch_q<PRF, 16>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? PIR_OK : fail_hip(e);
 }
 
-} // namespace
-
-extern "C" {
-
-int pir_answer(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, const uint32_t *d_table,
-               uint64_t rows, uint32_t dim, uint32_t *d_out, void *stream)
-{
-    return answer_one(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, (hipStream_t)stream);
-}
-
-int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t *d_keys, uint32_t key_stride,
-                     uint32_t *d_out, void *stream)
+template <class PRF>
+static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t *d_keys, uint32_t key_stride,
+                        uint32_t *d_out, void *stream)
 {
     if (!tables && n_tables)
         return PIR_EINVAL;
@@ -828,7 +879,7 @@ int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t
             w.n = n;
             cls[c].push_back(w);
         } else {
-            int st = answer_one(kp, T.n_keys, key_stride, T.d_table, T.rows, T.dim, op, (hipStream_t)stream);
+            int st = answer_one<PRF>(kp, T.n_keys, key_stride, T.d_table, T.rows, T.dim, op, (hipStream_t)stream);
             if (st != PIR_OK)
                 return st;
         }
@@ -836,11 +887,47 @@ int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t
     for (auto &v : cls)
         for (size_t i = 0; i < v.size(); i += MAX_TASKS) {
             const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, v.size() - i);
-            int st = launch_waves(v.data() + i, cnt, key_stride, (hipStream_t)stream, 8192);
+            int st = launch_waves<PRF>(v.data() + i, cnt, key_stride, (hipStream_t)stream, 8192);
             if (st != PIR_OK)
                 return st;
         }
     return PIR_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int pir_answer_prf(uint32_t prf_id, const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride,
+                   const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out, void *stream)
+{
+    if (prf_id == PIR_PRF_AES128)
+        return answer_one<AesPrf>(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, (hipStream_t)stream);
+    if (prf_id == PIR_PRF_CHACHA20)
+        return answer_one<ChaChaPrf>(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, (hipStream_t)stream);
+    return PIR_EINVAL;
+}
+
+int pir_answer(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, const uint32_t *d_table,
+               uint64_t rows, uint32_t dim, uint32_t *d_out, void *stream)
+{
+    return pir_answer_prf(PIR_PRF_AES128, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, stream);
+}
+
+int pir_answer_multi_prf(uint32_t prf_id, const pir_table_t *tables, uint32_t n_tables, const uint8_t *d_keys,
+                         uint32_t key_stride, uint32_t *d_out, void *stream)
+{
+    if (prf_id == PIR_PRF_AES128)
+        return answer_multi<AesPrf>(tables, n_tables, d_keys, key_stride, d_out, stream);
+    if (prf_id == PIR_PRF_CHACHA20)
+        return answer_multi<ChaChaPrf>(tables, n_tables, d_keys, key_stride, d_out, stream);
+    return PIR_EINVAL;
+}
+
+int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t *d_keys, uint32_t key_stride,
+                     uint32_t *d_out, void *stream)
+{
+    return pir_answer_multi_prf(PIR_PRF_AES128, tables, n_tables, d_keys, key_stride, d_out, stream);
 }
 
 int pir_check_status(void)

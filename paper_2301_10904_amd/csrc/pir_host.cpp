@@ -60,6 +60,52 @@ Block aes128_host(const Block &key, const Block &in)
     return out;
 }
 
+// ChaCha20 keystream block 0 under key s || s, nonce 0 (RFC 8439 state
+// layout): the two children's PRF outputs are its words 0..3 and 4..7.
+static void chacha_children_host(const Block &s, Block &p0, Block &p1)
+{
+    static const uint32_t sigma[4] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u};
+    uint32_t in[16], x[16];
+    for (int i = 0; i < 4; i++) {
+        in[i] = sigma[i];
+        in[4 + i] = s.w[i];
+        in[8 + i] = s.w[i];
+        in[12 + i] = 0;
+    }
+    memcpy(x, in, sizeof x);
+    auto qr = [&](int a, int b, int c, int d) {
+        x[a] += x[b];
+        x[d] = rotl32(x[d] ^ x[a], 16);
+        x[c] += x[d];
+        x[b] = rotl32(x[b] ^ x[c], 12);
+        x[a] += x[b];
+        x[d] = rotl32(x[d] ^ x[a], 8);
+        x[c] += x[d];
+        x[b] = rotl32(x[b] ^ x[c], 7);
+    };
+    for (int r = 0; r < 10; r++) {
+        for (int i = 0; i < 4; i++)
+            qr(i, 4 + i, 8 + i, 12 + i);
+        for (int i = 0; i < 4; i++)
+            qr(i, 4 + (i + 1) % 4, 8 + (i + 2) % 4, 12 + (i + 3) % 4);
+    }
+    for (int i = 0; i < 4; i++) {
+        p0.w[i] = x[i] + in[i];
+        p1.w[i] = x[4 + i] + in[4 + i];
+    }
+}
+
+// Both PRF outputs of a node with seed s under the PRF prf_id.
+static void prf_children_host(uint32_t prf_id, const Block &s, Block out[2])
+{
+    if (prf_id == PIR_PRF_CHACHA20) {
+        chacha_children_host(s, out[0], out[1]);
+    } else {
+        out[0] = aes128_host(s, counter_block(0));
+        out[1] = aes128_host(s, counter_block(1));
+    }
+}
+
 static Block load_block(const uint8_t *p)
 {
     Block b;
@@ -93,7 +139,15 @@ size_t dpf_key_size(uint32_t n)
 int dpf_gen(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16, uint8_t *key0,
             uint8_t *key1)
 {
+    return dpf_gen_prf(n, alpha, beta, seed16, PIR_PRF_AES128, key0, key1);
+}
+
+int dpf_gen_prf(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16, uint32_t prf_id,
+                uint8_t *key0, uint8_t *key1)
+{
     if (!key0 || !key1 || n < 1 || n > PIR_MAX_LOG_DOMAIN)
+        return PIR_EINVAL;
+    if (prf_id != PIR_PRF_AES128 && prf_id != PIR_PRF_CHACHA20)
         return PIR_EINVAL;
     if (alpha >> n)
         return PIR_EINVAL;
@@ -122,17 +176,17 @@ int dpf_gen(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16, ui
         keys[b][0] = PIR_KEY_VERSION;
         keys[b][1] = (uint8_t)b;
         keys[b][2] = (uint8_t)n;
-        keys[b][3] = 0; // AES-128
+        keys[b][3] = (uint8_t)prf_id;
     }
     store_block(key0 + 16, s0);
     store_block(key1 + 16, s1);
 
-    const Block x0 = counter_block(0), x1 = counter_block(1);
     for (uint32_t d = 1; d <= n; d++) {
         const unsigned c = (unsigned)((alpha >> (n - d)) & 1);
         const unsigned tau = s0.w[0] & 1u;
-        Block P0[2] = {aes128_host(s0, x0), aes128_host(s0, x1)};
-        Block P1[2] = {aes128_host(s1, x0), aes128_host(s1, x1)};
+        Block P0[2], P1[2];
+        prf_children_host(prf_id, s0, P0);
+        prf_children_host(prf_id, s1, P1);
         Block C[2][2]; // C[t][child]
 
         Block R = draw();

@@ -17,10 +17,13 @@ LIB_PATH = PKG / "libpir.so"
 
 PIR_OK, PIR_EINVAL, PIR_ENOMEM, PIR_EHIP, PIR_EKEY = 0, -1, -2, -3, -4
 MAX_DIM = 256
+PRF_AES128, PRF_CHACHA20 = 0, 1  # key byte 3
+PRFS = {"aes128": PRF_AES128, "chacha20": PRF_CHACHA20}
 
 # the exported C ABI, as declared in include/pir.h
-EXPORTS = ("dpf_key_size", "dpf_gen", "pir_answer", "pir_answer_multi", "pir_reconstruct",
-           "pir_check_status", "pir_strerror", "pir_last_hip_error")
+EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_prf",
+           "pir_answer_multi", "pir_answer_multi_prf", "pir_reconstruct", "pir_check_status",
+           "pir_strerror", "pir_last_hip_error")
 
 _lib = None
 
@@ -53,6 +56,17 @@ def load(path: Path | None = None):
     lib.dpf_key_size.argtypes = [ctypes.c_uint32]
     lib.dpf_gen.restype = ctypes.c_int
     lib.dpf_gen.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, u8p, u8p, u8p]
+    lib.dpf_gen_prf.restype = ctypes.c_int
+    lib.dpf_gen_prf.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, u8p,
+                                ctypes.c_uint32, u8p, u8p]
+    lib.pir_answer_prf.restype = ctypes.c_int
+    lib.pir_answer_prf.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
+                                   ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
+                                   ctypes.c_void_p]
+    lib.pir_answer_multi_prf.restype = ctypes.c_int
+    lib.pir_answer_multi_prf.argtypes = [ctypes.c_uint32, ctypes.POINTER(PirTable), ctypes.c_uint32,
+                                         ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
+                                         ctypes.c_void_p]
     lib.pir_answer.restype = ctypes.c_int
     lib.pir_answer.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
@@ -94,8 +108,18 @@ def log_domain(rows: int) -> int:
     return max(1, (int(rows) - 1).bit_length())
 
 
-def gen(n: int, alpha: int, beta: int = 1, seed: bytes | None = None):
-    """Client Gen: returns (key0, key1) as uint8 numpy arrays of key_size(n) bytes."""
+def prf_id(prf) -> int:
+    """PRF id from an id or a name ("aes128", "chacha20")."""
+    if isinstance(prf, str):
+        if prf not in PRFS:
+            raise ValueError(f"unknown PRF {prf!r}; known: {sorted(PRFS)}")
+        return PRFS[prf]
+    return int(prf)
+
+
+def gen(n: int, alpha: int, beta: int = 1, seed: bytes | None = None, prf=PRF_AES128):
+    """Client Gen: returns (key0, key1) as uint8 numpy arrays of key_size(n) bytes.
+    `prf` picks the tree's PRF (id or name); the random draws do not depend on it."""
     lib = load()
     ks = key_size(n)
     if ks == 0:
@@ -107,19 +131,19 @@ def gen(n: int, alpha: int, beta: int = 1, seed: bytes | None = None):
         sd = np.frombuffer(bytes(seed), np.uint8).copy()
         if sd.size != 16:
             raise ValueError("seed must be 16 bytes")
-    _check(lib.dpf_gen(n, alpha, beta & 0xFFFFFFFF, _u8(sd) if sd is not None else None,
-                       _u8(k0), _u8(k1)), "dpf_gen")
+    _check(lib.dpf_gen_prf(n, alpha, beta & 0xFFFFFFFF, _u8(sd) if sd is not None else None,
+                           prf_id(prf), _u8(k0), _u8(k1)), "dpf_gen")
     return k0, k1
 
 
-def gen_batch(n: int, alphas, seeds=None, beta: int = 1):
+def gen_batch(n: int, alphas, seeds=None, beta: int = 1, prf=PRF_AES128):
     """Keys for a batch of indices: (keys0, keys1), each uint8 [B, key_size(n)]."""
     B = len(alphas)
     ks = key_size(n)
     K0 = np.zeros((B, ks), np.uint8)
     K1 = np.zeros((B, ks), np.uint8)
     for q in range(B):
-        K0[q], K1[q] = gen(n, int(alphas[q]), beta, None if seeds is None else seeds[q])
+        K0[q], K1[q] = gen(n, int(alphas[q]), beta, None if seeds is None else seeds[q], prf)
     return K0, K1
 
 
@@ -142,12 +166,14 @@ def _check_dev(t, name, dtypes):
         raise ValueError(f"{name} must be contiguous")
 
 
-def answer(keys, table, out=None, stream=None):
+def answer(keys, table, out=None, stream=None, prf=PRF_AES128):
     """Server answer for one table: out[q] = sum_j Eval(keys[q], j) * table[j] mod 2^32.
 
     keys  : uint8 device tensor [B, stride] (stride a multiple of 16)
     table : int32/uint32 device tensor [rows, dim]
     out   : int32/uint32 device tensor [B, dim] (allocated if None)
+    prf   : the keys' PRF (id or name); a key of another PRF answers zero and
+            raises the flag of check_status()
     """
     import torch
 
@@ -161,12 +187,12 @@ def answer(keys, table, out=None, stream=None):
     _check_dev(out, "out", (torch.int32, torch.uint32))
     if tuple(out.shape) != (B, dim):
         raise ValueError("out must be [B, dim]")
-    _check(lib.pir_answer(keys.data_ptr(), B, stride, table.data_ptr(), rows, dim, out.data_ptr(),
-                          _stream_handle(stream)), "pir_answer")
+    _check(lib.pir_answer_prf(prf_id(prf), keys.data_ptr(), B, stride, table.data_ptr(), rows, dim,
+                              out.data_ptr(), _stream_handle(stream)), "pir_answer")
     return out
 
 
-def answer_multi(tables, key_counts, keys, out=None, stream=None):
+def answer_multi(tables, key_counts, keys, out=None, stream=None, prf=PRF_AES128):
     """Server answer over several tables in one call.
 
     tables     : list of int32/uint32 device tensors [rows_t, dim_t]
@@ -194,8 +220,8 @@ def answer_multi(tables, key_counts, keys, out=None, stream=None):
     _check_dev(out, "out", (torch.int32, torch.uint32))
     if out.numel() != total:
         raise ValueError("out has the wrong size")
-    _check(lib.pir_answer_multi(descs, len(tables), keys.data_ptr(), keys.shape[1], out.data_ptr(),
-                                _stream_handle(stream)), "pir_answer_multi")
+    _check(lib.pir_answer_multi_prf(prf_id(prf), descs, len(tables), keys.data_ptr(), keys.shape[1],
+                                    out.data_ptr(), _stream_handle(stream)), "pir_answer_multi")
     views, off = [], 0
     for t, c in zip(tables, key_counts):
         n = int(c) * t.shape[1]

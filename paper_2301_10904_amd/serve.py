@@ -53,7 +53,8 @@ class PirServer:
     """Resident tables plus a batching request loop on one GPU stream."""
 
     def __init__(self, hbm_budget_bytes: int, max_batch: int = 1024, max_queue: int = 4096,
-                 max_inflight: int = 3, max_batch_leaves: int = 1 << 30, device="cuda:0"):
+                 max_inflight: int = 3, max_batch_leaves: int = 1 << 30, device="cuda:0",
+                 prf=pir.PRF_AES128):
         import torch
 
         self.torch = torch
@@ -66,6 +67,7 @@ class PirServer:
         # tables enter in slices so a batch stays short and small tables keep
         # flowing under overload
         self.max_batch_leaves = int(max_batch_leaves)
+        self.prf = pir.prf_id(prf)  # the PRF every served key uses
         self.tables = []  # (tensor, rows, dim, n)
         self.resident_bytes = 0
         self.stream = torch.cuda.Stream(device=self.device)
@@ -175,7 +177,7 @@ class PirServer:
                 with torch.cuda.stream(self.stream):
                     slot["dkeys"][:nk].copy_(slot["hkeys"][:nk], non_blocking=True)
                     pir.answer_multi([t[0] for t in self.tables], counts, slot["dkeys"][:nk],
-                                     out=slot["dout"][:total_words], stream=self.stream)
+                                     out=slot["dout"][:total_words], stream=self.stream, prf=self.prf)
                     slot["hout"][:total_words].copy_(slot["dout"][:total_words], non_blocking=True)
                     slot["event"].record(self.stream)
                 slot["reqs"], slot["counts"] = reqs, counts

@@ -1,10 +1,11 @@
 """Build-time checks of the HIP device code (CPU only: hipcc cross-compiles).
 
-Every kernel that walks the tree reads its AES tables from LDS; if the
+Every kernel that walks the tree with AES reads its tables from LDS; if the
 compiler ever loses sight of those reads it may drop the table fill and the
-LDS allocation (a kernel would then read unallocated LDS).  The assembled
-kernels must each keep at least the 64 KiB table region, and none may spill
-more than a few loop-invariant words to scratch (64 bytes per lane).
+LDS allocation (a kernel would then read unallocated LDS).  The assembled AES
+kernels must each keep at least the 64 KiB table region; the ChaCha20 kernels
+need no table.  No kernel may spill more than a few loop-invariant words to
+scratch (64 bytes per lane).
 """
 import re
 import shutil
@@ -41,8 +42,12 @@ def kernel_metadata(asm):
 
 def test_tree_kernels_keep_their_lds_tables(device_asm):
     meta = kernel_metadata(device_asm)
-    tree = {k: v for k, v in meta.items() if "k_pir_" in k}
-    assert len(tree) >= 10, sorted(meta)
-    for name, (lds, scratch) in tree.items():
+    aes = {k: v for k, v in meta.items() if "k_pir_" in k and "AesPrf" in k}
+    chacha = {k: v for k, v in meta.items() if "k_pir_" in k and "ChaChaPrf" in k}
+    assert len(aes) >= 10 and len(chacha) == len(aes), sorted(meta)
+    for name, (lds, scratch) in aes.items():
         assert lds >= 65536, f"{name}: LDS {lds} bytes, the AES tables need 65536"
+        assert scratch <= 64, f"{name}: {scratch} bytes of scratch per lane"
+    for name, (lds, scratch) in chacha.items():
+        assert lds < 65536, f"{name}: LDS {lds} bytes; ChaCha20 needs no table"
         assert scratch <= 64, f"{name}: {scratch} bytes of scratch per lane"

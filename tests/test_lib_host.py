@@ -1,8 +1,8 @@
 """Host-side checks of libpir.so that need no GPU.
 
   - the library loads and exports every function include/pir.h declares;
-  - the library's Gen (its own AES and code) and the oracle's Gen produce
-    byte-identical keys from the same 16-byte seed;
+  - the library's Gen (its own AES, ChaCha20 and code) and the oracle's Gen
+    produce byte-identical keys from the same 16-byte seed, for both PRFs;
   - argument validation returns PIR_EINVAL before anything is launched;
   - reconstruction and status strings.
 """
@@ -55,6 +55,27 @@ def test_gen_matches_oracle_bytes(O, n):
         assert (k0 == o0).all() and (k1 == o1).all(), (n, alpha, beta)
 
 
+@pytest.mark.parametrize("n", [1, 3, 9, 20, 32])
+def test_gen_chacha_matches_oracle_bytes(O, n):
+    rng = np.random.default_rng([n, 20])
+    for trial in range(3):
+        alpha = int(rng.integers(0, 1 << n))
+        beta = int(rng.integers(0, 2**32)) if trial else 1
+        seed = rng.integers(0, 256, 16, dtype=np.uint8).tobytes()
+        k0, k1 = pir.gen(n, alpha, beta, seed, prf="chacha20")
+        o0, o1 = O.gen(n, alpha, beta, seed, prf_id=1)
+        assert k0[3] == pir.PRF_CHACHA20
+        assert (k0 == o0).all() and (k1 == o1).all(), (n, alpha, beta)
+
+
+def test_gen_rejects_unknown_prf(lib):
+    with pytest.raises(pir.PirError) as e:
+        pir.gen(5, 3, 1, bytes(16), prf=2)
+    assert e.value.status == pir.PIR_EINVAL
+    with pytest.raises(ValueError):
+        pir.gen(5, 3, 1, bytes(16), prf="salsa20")
+
+
 def test_gen_without_seed_is_random_and_correct(O):
     k0, k1 = pir.gen(6, 17)
     k0b, _ = pir.gen(6, 17)
@@ -102,8 +123,12 @@ def test_answer_validation_without_gpu(lib):
     ]
     for c in cases:
         assert lib.pir_answer(*c, None) == pir.PIR_EINVAL, c
+        for prf in (pir.PRF_AES128, pir.PRF_CHACHA20):
+            assert lib.pir_answer_prf(prf, *c, None) == pir.PIR_EINVAL, (prf, c)
     # zero keys is a no-op
     assert lib.pir_answer(None, 0, ks, None, 1024, 4, None, None) == pir.PIR_OK
+    # an unknown PRF id is rejected even where the call is otherwise valid
+    assert lib.pir_answer_prf(2, fake, 1, ks, fake, 1024, 4, fake, None) == pir.PIR_EINVAL
 
 
 def test_answer_multi_validation_without_gpu(lib):
@@ -115,3 +140,5 @@ def test_answer_multi_validation_without_gpu(lib):
     assert lib.pir_answer_multi(T, 1, fake, ks, fake, None) == pir.PIR_EINVAL
     T = (pir.PirTable * 1)(pir.PirTable(fake, 4096, 8, 0))
     assert lib.pir_answer_multi(T, 1, None, ks, None, None) == pir.PIR_OK
+    assert lib.pir_answer_multi_prf(pir.PRF_CHACHA20, T, 1, None, ks, None, None) == pir.PIR_OK
+    assert lib.pir_answer_multi_prf(5, T, 1, None, ks, None, None) == pir.PIR_EINVAL
