@@ -61,6 +61,9 @@ def _bind(lib):
         "or_answer_batch": (ctypes.c_int, [u8p, ctypes.c_uint32, ctypes.c_size_t, u32p,
                                            ctypes.c_uint64, ctypes.c_uint32, u32p,
                                            ctypes.c_int]),
+        "or_answer_bins": (ctypes.c_int, [u8p, ctypes.c_uint32, ctypes.c_size_t, u32p,
+                                          ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32, u32p,
+                                          ctypes.c_int]),
         "or_reconstruct": (None, [u32p, u32p, ctypes.c_uint32, u32p]),
         "or_count_prf": (ctypes.c_uint64, []),
         "or_count_drbg": (ctypes.c_uint64, []),
@@ -222,6 +225,23 @@ class Oracle:
         if self.lib.or_answer_batch(_u8(keys), B, stride, _u32(table), rows, dim,
                                     _u32(out), nt):
             raise ValueError("or_answer_batch rejected its arguments")
+        return out
+
+    def answer_bins(self, keys: np.ndarray, table: np.ndarray, bin_log: int, n_clients: int,
+                    nthreads: int | None = None) -> np.ndarray:
+        """Partial batch retrieval, server side (section 4.1): keys [n_clients *
+        n_bins, stride] ordered client-major; returns [n_clients, n_bins, dim]."""
+        keys = np.ascontiguousarray(keys, dtype=np.uint8)
+        table = np.ascontiguousarray(table, dtype=np.uint32)
+        rows, dim = table.shape
+        n_bins = -(-rows // (1 << bin_log))
+        if keys.shape[0] != n_clients * n_bins:
+            raise ValueError("keys must hold n_clients * n_bins rows")
+        out = np.zeros((n_clients, n_bins, dim), np.uint32)
+        nt = nthreads or os.cpu_count() or 1
+        if self.lib.or_answer_bins(_u8(keys), n_clients, keys.shape[1], _u32(table), rows, dim,
+                                   bin_log, _u32(out), nt):
+            raise ValueError("or_answer_bins rejected its arguments")
         return out
 
     def reconstruct(self, a0: np.ndarray, a1: np.ndarray) -> np.ndarray:

@@ -347,6 +347,70 @@ int or_answer_batch(const uint8_t *keys, uint32_t nkeys, size_t stride,
     return st;
 }
 
+/* Partial batch retrieval, server side (paper section 4.1): the table is cut
+ * into bins of 2^bin_log consecutive rows (the last bin may be shorter) and
+ * key (c, b) -- client c, bin b, at keys + (c * n_bins + b) * stride -- is a
+ * DPF over the domain of one bin.  Its answer is that key's answer over the
+ * bin's rows: ans[c][b][k] = sum_{j < rows_b} Eval(key, j) * T[b 2^bin_log + j][k]. */
+struct bins_job {
+    const uint8_t *keys;
+    uint32_t n_clients, n_bins, bin_log, dim;
+    size_t stride;
+    const uint32_t *table;
+    uint64_t rows;
+    uint32_t *ans;
+    int nthreads, tid, status;
+};
+
+static void *bins_worker(void *arg)
+{
+    struct bins_job *jb = arg;
+    uint64_t total = (uint64_t)jb->n_clients * jb->n_bins;
+    for (uint64_t i = (uint64_t)jb->tid; i < total; i += (uint64_t)jb->nthreads) {
+        uint64_t b = i % jb->n_bins;
+        uint64_t first = b << jb->bin_log;
+        uint64_t rows_b = jb->rows - first;
+        if (rows_b > ((uint64_t)1 << jb->bin_log))
+            rows_b = (uint64_t)1 << jb->bin_log;
+        const uint8_t *key = jb->keys + i * jb->stride;
+        if (key[2] != jb->bin_log ||
+            or_answer(key, jb->table + first * jb->dim, rows_b, jb->dim, jb->ans + i * jb->dim))
+            jb->status = -1;
+    }
+    return NULL;
+}
+
+int or_answer_bins(const uint8_t *keys, uint32_t n_clients, size_t stride, const uint32_t *table,
+                   uint64_t rows, uint32_t dim, uint32_t bin_log, uint32_t *ans, int nthreads)
+{
+    if (!keys || !table || !ans || rows == 0 || dim == 0 || bin_log < 1 || bin_log > 30)
+        return -1;
+    uint64_t n_bins = (rows + ((uint64_t)1 << bin_log) - 1) >> bin_log;
+    if (n_bins > 0xffffffffu)
+        return -1;
+    if (nthreads < 1)
+        nthreads = 1;
+    if (nthreads > 256)
+        nthreads = 256;
+    struct bins_job jobs[256];
+    pthread_t th[256];
+    int started[256];
+    for (int i = 0; i < nthreads; i++) {
+        jobs[i] = (struct bins_job){keys, n_clients, (uint32_t)n_bins, bin_log, dim, stride,
+                                    table, rows, ans, nthreads, i, 0};
+        started[i] = pthread_create(&th[i], NULL, bins_worker, &jobs[i]) == 0;
+        if (!started[i])
+            bins_worker(&jobs[i]);
+    }
+    int st = 0;
+    for (int i = 0; i < nthreads; i++) {
+        if (started[i])
+            pthread_join(th[i], NULL);
+        st |= jobs[i].status;
+    }
+    return st;
+}
+
 void or_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim, uint32_t *out)
 {
     for (uint32_t k = 0; k < dim; k++)

@@ -85,6 +85,12 @@ int or_answer(const uint8_t *key, const uint32_t *table, uint64_t rows,
 int or_answer_batch(const uint8_t *keys, uint32_t nkeys, size_t stride,
                     const uint32_t *table, uint64_t rows, uint32_t dim,
                     uint32_t *ans, int nthreads);
+/* Partial batch retrieval (section 4.1), server side: bins of 2^bin_log rows,
+ * key (c, b) at keys + (c * n_bins + b) * stride with n_bins = ceil(rows /
+ * 2^bin_log), every key over the bin domain (n = bin_log);
+ * ans[(c * n_bins + b) * dim + k] = sum_{j < rows_b} Eval(key, j) T[b 2^bin_log + j][k]. */
+int or_answer_bins(const uint8_t *keys, uint32_t n_clients, size_t stride, const uint32_t *table,
+                   uint64_t rows, uint32_t dim, uint32_t bin_log, uint32_t *ans, int nthreads);
 void or_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim,
                     uint32_t *out);
 

@@ -153,6 +153,19 @@ __device__ __forceinline__ Seed child_on_path(const PRF &P, const KeyView &K, co
     return Seed{{a[0] ^ w.x, a[1] ^ w.y, a[2] ^ w.z, a[3] ^ w.w}};
 }
 
+// Logical block index of this workgroup.  The hardware deals workgroups to the
+// 8 XCDs in turn (block b to XCD b mod 8), and each XCD has its own L2; work
+// items that read the same table rows sit at consecutive logical indices, so
+// the map gives every XCD one contiguous range of logical blocks (a bijection
+// on [0, gridDim.x)) and rows shared by neighbouring blocks stay in one L2.
+__device__ __forceinline__ uint32_t xcd_block()
+{
+    constexpr uint32_t XCDS = 8;
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t x = b % XCDS, k = b / XCDS, per = nb / XCDS, extra = nb % XCDS;
+    return x * per + (x < extra ? x : extra) + k;
+}
+
 __global__ void k_fill_zero(uint32_t *out, size_t count)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -182,8 +195,9 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63, wave = tid >> 6;
-    const uint32_t grp = blockIdx.x % g.n_groups;
-    const uint32_t chunk = blockIdx.x / g.n_groups;
+    const uint32_t blk = xcd_block();
+    const uint32_t grp = blk % g.n_groups;
+    const uint32_t chunk = blk / g.n_groups;
     const uint64_t row_base = (uint64_t)chunk << g.H;
     const PRF P(sm.tab, lane);
 
@@ -532,7 +546,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();
     }
 
-    const uint32_t item0 = blockIdx.x * NW3 + wave;
+    const uint32_t item0 = xcd_block() * NW3 + wave;
     if (item0 >= tasks.n_items)
         return; // whole wave; no barrier follows
     uint32_t ti = 0; // the table this item belongs to (tasks are in item order)

@@ -2,8 +2,8 @@
 
 Each case copies the oracle's C sources, plants one mistake by text
 substitution, builds the copy on the CPU and runs the pin suites
-(test_oracle_aes.py, test_oracle_dpf.py, test_oracle_chacha.py) against it:
-they must fail.
+(test_oracle_aes.py, test_oracle_dpf.py, test_oracle_chacha.py,
+test_oracle_batch.py) against it: they must fail.
 """
 import os
 import shutil
@@ -44,6 +44,8 @@ MUTANTS = {
     "chacha_child_same_half": ("dpf_ref.c", "memcpy(out, blk + 16 * (x % 4), 16);", "memcpy(out, blk, 16);"),
     "chacha_tree_uses_aes": ("dpf_ref.c", "or_prf_by(key[3], parent, (uint64_t)c, p);",
                              "or_prf_by(0, parent, (uint64_t)c, p);"),
+    "bins_first_row_not_scaled": ("dpf_ref.c", "uint64_t first = b << jb->bin_log;", "uint64_t first = b;"),
+    "bins_keys_bin_major": ("dpf_ref.c", "uint64_t b = i % jb->n_bins;", "uint64_t b = i / jb->n_clients;"),
     "answer_skips_last_row": ("dpf_ref.c", "for (uint64_t j = 0; j < rows; j++)\n        for (uint32_t k",
                               "for (uint64_t j = 0; j + 1 < rows; j++)\n        for (uint32_t k"),
 }
@@ -62,6 +64,6 @@ def test_pins_catch_planted_mistake(name, tmp_path):
     r = subprocess.run(
         [sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
          str(ROOT / "tests" / "test_oracle_aes.py"), str(ROOT / "tests" / "test_oracle_dpf.py"),
-         str(ROOT / "tests" / "test_oracle_chacha.py")],
+         str(ROOT / "tests" / "test_oracle_chacha.py"), str(ROOT / "tests" / "test_oracle_batch.py")],
         env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"planted mistake {name} passed every pin:\n{r.stdout[-2000:]}"
