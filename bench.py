@@ -163,10 +163,12 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="keys of the workload the oracle answers for the CPU baseline (x8 for ChaCha20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="batch", choices=["batch", "small", "multi", "large", "serve"],
+    ap.add_argument("--mode", default="batch", choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull"],
                     help="batch: 2^20 x 64, 512 pairs (the default line); small: 2^14 x 16, one pair; "
                          "multi: 8 tables 2^16..2^23 x 32, ragged Zipf batches in one call; "
-                         "large: 2^25 x 64 (8 GiB), 512..2048 pairs; serve: Poisson request loop over 4 tables")
+                         "large: 2^25 x 64 (8 GiB), 512..2048 pairs; serve: Poisson request loop over 4 tables; "
+                         "pbr: partial batch retrieval on 2^20 x 64, bins of 2^10..2^14; "
+                         "hotfull: hot table + full table with fixed query budgets")
     ap.add_argument("--prf", default="aes128", choices=["aes128", "chacha20"],
                     help="the DPF tree's PRF (section 3.2.6): AES-128 (default) or ChaCha20")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
@@ -408,9 +410,122 @@ def other_modes(args):
                     single_query={"qps": round(1 / sec1, 1), "p50_ms": round(percentile(ms1, 50), 3),
                                   "p99_ms": round(percentile(ms1, 99), 3)},
                     config={"workload": "one table 2^25 x 64 uint32 (8 GiB) resident, 1024/2048/4096 keys"})
+    elif args.mode == "pbr":
+        line.update(pbr_sweep(args))
+    elif args.mode == "hotfull":
+        line.update(hotfull_run(args))
     else:
         line.update(serve_sweep(args))
     print(json.dumps(line), flush=True)
+
+
+def pbr_sweep(args):
+    """Partial batch retrieval (section 4.1) on a 2^20 x 64 table: each client
+    wants 64 Zipf(1.05)-distributed rows and sends one key per bin; 128 clients
+    per server, both servers' keys in one call."""
+    import torch
+
+    from paper_2301_10904_amd import client, pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    rows, dim, seed, clients, wanted_n = 1 << 20, 64, 21, 128, 64
+    T = W.make_table(rows, dim, seed, device=dev)
+    perm = W.row_permutation(rows, seed)  # popular rows scattered over the bins
+    runs = []
+    ok = True
+    for bin_log in (10, 12, 14):
+        nb = pir.n_bins(rows, bin_log)
+        K0, K1, served, n_served, n_dropped = [], [], [], 0, 0
+        for c in range(clients):
+            wanted = perm[W.zipf_indices(rows, wanted_n, seed * 1000 + c)]
+            wanted = wanted[np.sort(np.unique(wanted, return_index=True)[1])]  # distinct rows, in order
+            k0, k1, sv, dr = client.pbr_keys(wanted, rows, bin_log, W.key_seeds(nb, seed * 7919 + c), prf=args.prf)
+            K0.append(k0)
+            K1.append(k1)
+            served.append(sv)
+            n_served += int((sv >= 0).sum())
+            n_dropped += len(dr)
+        keys = torch.from_numpy(np.concatenate(K0 + K1)).to(dev)
+        out, views = pir.answer_bins([T, T], [clients, clients], [bin_log, bin_log], keys, prf=args.prf)
+        sec, ms = time_launches(lambda: pir.answer_bins([T, T], [clients, clients], [bin_log, bin_log], keys,
+                                                        out=out, prf=args.prf), 5, 1)
+        g0, g1 = (v.cpu().numpy() for v in views)
+        for c in range(0, clients, 9):
+            got = client.pbr_read(g0[c], g1[c], served[c])
+            idx = sorted(got)
+            ok &= bool((np.stack([got[x] for x in idx]) == W.table_rows_np(idx, dim, seed)).all())
+        runs.append({"bin_rows": 1 << bin_log, "bins": nb, "keys_per_call": 2 * clients * nb,
+                     "ms_per_call": round(sec * 1e3, 3),
+                     "client_batches_per_s": round(clients / sec, 1),
+                     "entries_retrieved_per_s": round(n_served / sec, 1),
+                     "served_per_client": round(n_served / clients, 2),
+                     "drop_rate": round(n_dropped / max(1, n_served + n_dropped), 4),
+                     "server_keys_per_s": round(2 * clients * nb / sec, 1)})
+    best = max(r["entries_retrieved_per_s"] for r in runs)
+    return {"value": best, "unit": "entries retrieved/s", "exact": ok, "pbr": runs,
+            "config": {"workload": f"partial batch retrieval, one table 2^20 x 64 uint32, {clients} clients per "
+                                   f"server (both servers' keys in one call), {wanted_n} Zipf(1.05) wanted rows "
+                                   "per client (popularity ranks scattered over the rows by a seeded permutation; "
+                                   "repeats removed), one key per bin", "prf": args.prf}}
+
+
+def hotfull_run(args):
+    """Hot/full split (section 4.2): full table 2^22 x 32, hot table of the 2^18
+    most frequent rows of a Zipf(1.05) access log, Q_hot = 8 and Q_full = 2
+    queries per client for 8 wanted rows, 256 clients per server."""
+    import torch
+
+    from paper_2301_10904_amd import client, pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    rows, dim, seed, clients, q_hot, q_full, want = 1 << 22, 32, 31, 256, 8, 2, 8
+    T = W.make_table(rows, dim, seed, device=dev)
+    log = W.zipf_indices(rows, 1 << 20, seed)
+    hot_rows, hot_of = client.hot_rows_by_frequency(np.bincount(log, minlength=rows), 1 << 18)
+    H = T[torch.from_numpy(hot_rows).to(dev)].contiguous()  # built once, ahead of serving
+    n_hot, n_full = 18, 22
+    KH, KF, plans, dropped = [[], []], [[], []], [], 0
+    for c in range(clients):
+        wanted = W.zipf_indices(rows, want, seed * 100 + c)
+        ha, fa, sh, sf, dr = client.hot_full_plan(wanted, hot_of, q_hot, q_full)
+        h0, h1 = pir.gen_batch(n_hot, ha, W.key_seeds(q_hot, seed * 7 + c), prf=args.prf)
+        f0, f1 = pir.gen_batch(n_full, fa, W.key_seeds(q_full, seed * 11 + c), prf=args.prf)
+        KH[0].append(h0), KH[1].append(h1), KF[0].append(f0), KF[1].append(f1)
+        plans.append((sh, sf))
+        dropped += len(dr)
+    stride = (pir.key_size(n_full) + 15) // 16 * 16
+    pad = lambda k: np.pad(k, ((0, 0), (0, stride - k.shape[1])))
+    keys = torch.from_numpy(np.concatenate([pad(np.concatenate(KH[0])), pad(np.concatenate(KF[0])),
+                                            pad(np.concatenate(KH[1])), pad(np.concatenate(KF[1]))])).to(dev)
+    tabs, counts, logs = [H, T, H, T], [clients * q_hot, clients * q_full] * 2, [n_hot, n_full] * 2
+    out, views = pir.answer_bins(tabs, counts, logs, keys, prf=args.prf)
+    sec, ms = time_launches(lambda: pir.answer_bins(tabs, counts, logs, keys, out=out, prf=args.prf), 5, 1)
+    v = [x.cpu().numpy().view(np.uint32)[:, 0] for x in views]
+    hot = ((v[0].astype(np.uint64) + v[2]) & 0xFFFFFFFF).astype(np.uint32)
+    full = ((v[1].astype(np.uint64) + v[3]) & 0xFFFFFFFF).astype(np.uint32)
+    served, ok = 0, True
+    for c, (sh, sf) in enumerate(plans):
+        for i, x in enumerate(sh):
+            if x >= 0:
+                served += 1
+                ok &= bool((hot[c * q_hot + i] == W.table_rows_np([x], dim, seed)[0]).all())
+        for i, x in enumerate(sf):
+            if x >= 0:
+                served += 1
+                ok &= bool((full[c * q_full + i] == W.table_rows_np([x], dim, seed)[0]).all())
+    # the same number of queries (Q = 10 per client and server) all on the full table
+    k_all = torch.from_numpy(np.concatenate([pad(np.concatenate(KF[0]))] * 5 +
+                                            [pad(np.concatenate(KF[1]))] * 5)).to(dev)
+    sec_full, _ = time_launches(lambda: pir.answer(k_all, T, prf=args.prf), 3, 1)
+    return {"value": round(clients / sec, 1), "unit": "client batches/s", "exact": ok,
+            "ms_per_call": round(sec * 1e3, 3), "entries_retrieved_per_s": round(served / sec, 1),
+            "drop_rate": round(dropped / (clients * want), 4),
+            "full_table_only_ms_for_same_key_count": round(sec_full * 1e3, 3),
+            "config": {"workload": f"hot/full split: full table 2^22 x 32 uint32, hot table 2^18 rows (top rows of a "
+                                   f"Zipf(1.05) log), Q_hot={q_hot}, Q_full={q_full} per client for {want} wanted rows, "
+                                   f"{clients} clients per server, both servers in one call", "prf": args.prf}}
 
 
 def serve_sweep(args):

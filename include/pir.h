@@ -147,6 +147,39 @@ int pir_answer_multi_prf(uint32_t prf_id, const pir_table_t *tables, uint32_t n_
                          const uint8_t *d_keys, uint32_t key_stride, uint32_t *d_out,
                          void *stream);
 
+/* Partial batch retrieval, server side (paper section 4.1): a table is cut
+ * into n_bins = ceil(rows / 2^bin_log) bins of 2^bin_log consecutive rows (the
+ * last may be shorter) and every client sends one DPF key per bin, over the
+ * bin's domain (n = bin_log); key (c, b) answers
+ *     sum_{j < rows_b} Eval(key, j) * T[b 2^bin_log + j][k]   (mod 2^32).
+ * A client wanting up to n_bins entries in distinct bins retrieves them all at
+ * the cost of one full-table query.  Which entry each bin serves, and dummy
+ * keys for bins it does not need, are the client's business. */
+#define PIR_BINS_MIN_LOG 3  /* bins of at least 8 rows   */
+#define PIR_BINS_MAX_DIM 64 /* rows of at most 64 words  */
+typedef struct {
+    const uint32_t *d_table; /* row-major uint32 [rows][dim] in HBM, 4-byte aligned */
+    uint64_t rows;           /* 1 <= rows <= 2^32 */
+    uint32_t dim;            /* 1..PIR_BINS_MAX_DIM */
+    uint32_t n_clients;      /* clients querying this table (may be 0) */
+    uint32_t bin_log;        /* PIR_BINS_MIN_LOG..32; >= ceil(log2 rows) is one bin */
+} pir_bins_t;
+
+/* Server side answer of partial batch retrieval over one or more tables in
+ * one stream-ordered call.
+ *   tables     host array of n_tables descriptors
+ *   d_keys     keys grouped by table in the order of `tables`; within table
+ *              t, client-major: key (c, b) is the (c * n_bins_t + b)-th key
+ *              of the table; every key carries n = bin_log_t and prf_id;
+ *              stride and alignment as for pir_answer
+ *   d_out      answers in key order, dim_t words each; fully overwritten
+ * Bad key headers as for pir_answer.  PIR_EINVAL for an unknown prf_id, bad
+ * sizes (including dim > PIR_BINS_MAX_DIM or bin_log < PIR_BINS_MIN_LOG),
+ * null pointers or misalignment; nothing is launched then. */
+int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables,
+                    const uint8_t *d_keys, uint32_t key_stride, uint32_t *d_out,
+                    void *stream);
+
 /* Client side reconstruction (paper section 3.1): out[k] = a0[k] + a1[k]
  * mod 2^32 for k < dim; host buffers.  PIR_EINVAL on null pointers. */
 int pir_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim, uint32_t *out);

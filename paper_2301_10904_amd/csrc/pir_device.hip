@@ -520,13 +520,17 @@ __device__ __forceinline__ void load_cols(const uint32_t *__restrict__ table, ui
     }
 }
 
-// One table's share of a wave-kernel launch.
+// One table's share of a wave-kernel launch.  The table is cut into n_bins
+// bins of 2^n rows (the last may be shorter; one bin for a whole-table query)
+// and every client sends one key per bin: key (c, b) at keys + (c n_bins + b)
+// * stride, answer at out + (c n_bins + b) * dim.
 struct WaveTask {
     const uint32_t *table; // row-major uint32 [rows][dim]
     const uint8_t *keys;   // this table's first key
     uint32_t *out;         // this table's first answer word
     uint64_t rows;
     uint32_t dim, n_keys, n, h, n_groups, item_begin;
+    uint32_t n_bins, chunks_per_bin; // n_keys counts clients
 };
 constexpr int MAX_TASKS = 16;
 struct WaveTasks {
@@ -554,18 +558,23 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
         ti++;
     const WaveTask &g = tasks.t[ti];
     const uint32_t item = item0 - g.item_begin;
-    const uint8_t *__restrict__ keys = g.keys;
-    const uint32_t *__restrict__ table = g.table;
-    uint32_t *__restrict__ out = g.out;
-    const uint64_t rows = g.rows;
     const uint32_t dim = g.dim, n_keys = g.n_keys;
-    const uint32_t grp = item % g.n_groups, chunk = item / g.n_groups;
+    const uint32_t grp = item % g.n_groups, bin_chunk = item / g.n_groups;
+    const uint32_t bin = bin_chunk / g.chunks_per_bin, chunk = bin_chunk % g.chunks_per_bin;
+    // this bin's rows, keys (one per client, n_bins apart) and answers
+    const uint64_t first_row = (uint64_t)bin << g.n;
+    const uint64_t rows_left = g.rows - first_row;
+    const uint64_t rows = rows_left < ((uint64_t)1 << g.n) ? rows_left : ((uint64_t)1 << g.n);
+    const uint32_t *__restrict__ table = g.table + first_row * dim;
+    const uint8_t *__restrict__ keys = g.keys + (size_t)bin * stride;
+    uint32_t *__restrict__ out = g.out + (size_t)bin * dim;
+    const size_t key_step = (size_t)g.n_bins * stride, out_step = (size_t)g.n_bins * dim;
     const uint32_t q = lane & 15, sub = lane >> 4;
     const uint32_t kq = grp * 16 + q;
     const uint32_t h = g.h;
 
     uint32_t ok = 0;
-    const KeyView K{keys + (size_t)(kq < n_keys ? kq : 0) * stride};
+    const KeyView K{keys + (size_t)(kq < n_keys ? kq : 0) * key_step};
     if (kq < n_keys) {
         const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
         const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
@@ -677,7 +686,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
             uint32_t v = (uint32_t)tot[t][i];
             if (kok == 2)
                 v = 0u - v;
-            atomicAdd(&out[(size_t)(grp * 16 + key) * dim + col], v);
+            atomicAdd(&out[(size_t)(grp * 16 + key) * out_step + col], v);
         }
     }
 }
@@ -734,15 +743,16 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipSt
     for (uint32_t i = 0; i < count; i++) {
         WaveTask &t = ts[i];
         t.n_groups = (t.n_keys + 15) / 16;
+        const uint64_t bin_rows = std::min<uint64_t>(t.rows, (uint64_t)1 << t.n);
+        auto chunks_per_bin = [&](uint32_t hh) { return (bin_rows + ((uint64_t)4 << hh) - 1) / ((uint64_t)4 << hh); };
         uint32_t h = std::min<uint32_t>(HMAX3, t.n - 2);
         // enough wave items to fill every CU several times (single table)
-        while (count == 1 && h > 3 &&
-               ((t.rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h)) * t.n_groups < min_items)
+        while (count == 1 && h > 3 && (uint64_t)t.n_bins * chunks_per_bin(h) * t.n_groups < min_items)
             h--;
         t.h = h;
-        const uint64_t chunks = (t.rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h);
+        t.chunks_per_bin = (uint32_t)chunks_per_bin(h);
         t.item_begin = (uint32_t)items;
-        items += chunks * t.n_groups;
+        items += (uint64_t)t.n_bins * t.chunks_per_bin * t.n_groups;
         if (items >= ((uint64_t)1 << 31))
             return PIR_ENOMEM;
         W.t[i] = t;
@@ -750,7 +760,7 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipSt
     W.count = count;
     W.n_items = (uint32_t)items;
     for (uint32_t i = 0; i < count; i++) {
-        const size_t words = (size_t)ts[i].n_keys * ts[i].dim;
+        const size_t words = (size_t)ts[i].n_keys * ts[i].n_bins * ts[i].dim;
         const uint32_t blocks = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
         hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, ts[i].out, words);
     }
@@ -813,6 +823,7 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
         t.dim = dim;
         t.n_keys = n_keys;
         t.n = n;
+        t.n_bins = 1;
         return launch_waves<PRF>(&t, 1, key_stride, st, 8192);
     }
 
@@ -865,7 +876,8 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
             T.rows > ((uint64_t)1 << PIR_MAX_LOG_DOMAIN) || !d_keys || !d_out)
             return PIR_EINVAL;
         uint32_t n = T.rows <= 2 ? 1 : ceil_log2(T.rows);
-        if (key_stride % 16 || key_stride < dpf_key_size(n))
+        if (key_stride % 16 || key_stride < dpf_key_size(n) || ((uintptr_t)d_keys % 16) ||
+            ((uintptr_t)T.d_table % 4) || ((uintptr_t)d_out % 4))
             return PIR_EINVAL;
     }
     // tables the wave kernel takes go out grouped by column class, up to
@@ -891,6 +903,7 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
             w.dim = T.dim;
             w.n_keys = T.n_keys;
             w.n = n;
+            w.n_bins = 1;
             cls[c].push_back(w);
         } else {
             int st = answer_one<PRF>(kp, T.n_keys, key_stride, T.d_table, T.rows, T.dim, op, (hipStream_t)stream);
@@ -908,9 +921,71 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
     return PIR_OK;
 }
 
+// Partial batch retrieval: every table cut into bins of 2^bin_log rows, one
+// key per (client, bin), all on the wave kernel.
+template <class PRF>
+static int answer_bins(const pir_bins_t *tables, uint32_t n_tables, const uint8_t *d_keys, uint32_t key_stride,
+                       uint32_t *d_out, void *stream)
+{
+    if (!tables && n_tables)
+        return PIR_EINVAL;
+    for (uint32_t t = 0; t < n_tables; t++) {
+        const pir_bins_t &T = tables[t];
+        if (T.n_clients == 0)
+            continue;
+        if (!T.d_table || !d_keys || !d_out || T.rows == 0 || T.dim == 0 || T.dim > PIR_BINS_MAX_DIM ||
+            T.rows > ((uint64_t)1 << PIR_MAX_LOG_DOMAIN) || T.bin_log < PIR_BINS_MIN_LOG ||
+            T.bin_log > PIR_MAX_LOG_DOMAIN)
+            return PIR_EINVAL;
+        if (key_stride % 16 || key_stride < dpf_key_size(T.bin_log) || ((uintptr_t)d_keys % 16) ||
+            ((uintptr_t)T.d_table % 4) || ((uintptr_t)d_out % 4))
+            return PIR_EINVAL;
+    }
+    std::vector<WaveTask> cls[6];
+    size_t key_off = 0, out_off = 0;
+    for (uint32_t t = 0; t < n_tables; t++) {
+        const pir_bins_t &T = tables[t];
+        const uint64_t n_bins = (T.rows + ((uint64_t)1 << T.bin_log) - 1) >> T.bin_log;
+        const uint8_t *kp = d_keys + key_off * key_stride;
+        uint32_t *op = d_out + out_off;
+        key_off += (size_t)T.n_clients * n_bins;
+        out_off += (size_t)T.n_clients * n_bins * T.dim;
+        if (T.n_clients == 0)
+            continue;
+        WaveTask w;
+        w.table = T.d_table;
+        w.keys = kp;
+        w.out = op;
+        w.rows = T.rows;
+        w.dim = T.dim;
+        w.n_keys = T.n_clients;
+        w.n = T.bin_log;
+        w.n_bins = (uint32_t)n_bins;
+        cls[wave_class(T.dim)].push_back(w);
+    }
+    for (auto &v : cls)
+        for (size_t i = 0; i < v.size(); i += MAX_TASKS) {
+            const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, v.size() - i);
+            int st = launch_waves<PRF>(v.data() + i, cnt, key_stride, (hipStream_t)stream, 8192);
+            if (st != PIR_OK)
+                return st;
+        }
+    return PIR_OK;
+}
+
 } // namespace
 
 extern "C" {
+
+int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables, const uint8_t *d_keys,
+                    uint32_t key_stride, uint32_t *d_out, void *stream)
+{
+    if (prf_id == PIR_PRF_AES128)
+        return answer_bins<AesPrf>(tables, n_tables, d_keys, key_stride, d_out, stream);
+    if (prf_id == PIR_PRF_CHACHA20)
+        return answer_bins<ChaChaPrf>(tables, n_tables, d_keys, key_stride, d_out, stream);
+    return PIR_EINVAL;
+}
 
 int pir_answer_prf(uint32_t prf_id, const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride,
                    const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out, void *stream)

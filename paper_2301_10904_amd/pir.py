@@ -22,8 +22,9 @@ PRFS = {"aes128": PRF_AES128, "chacha20": PRF_CHACHA20}
 
 # the exported C ABI, as declared in include/pir.h
 EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_prf",
-           "pir_answer_multi", "pir_answer_multi_prf", "pir_reconstruct", "pir_check_status",
-           "pir_strerror", "pir_last_hip_error")
+           "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_reconstruct",
+           "pir_check_status", "pir_strerror", "pir_last_hip_error")
+BINS_MIN_LOG, BINS_MAX_DIM = 3, 64
 
 _lib = None
 
@@ -38,6 +39,11 @@ class PirError(RuntimeError):
 class PirTable(ctypes.Structure):
     _fields_ = [("d_table", ctypes.c_void_p), ("rows", ctypes.c_uint64),
                 ("dim", ctypes.c_uint32), ("n_keys", ctypes.c_uint32)]
+
+
+class PirBins(ctypes.Structure):
+    _fields_ = [("d_table", ctypes.c_void_p), ("rows", ctypes.c_uint64), ("dim", ctypes.c_uint32),
+                ("n_clients", ctypes.c_uint32), ("bin_log", ctypes.c_uint32)]
 
 
 def load(path: Path | None = None):
@@ -73,6 +79,9 @@ def load(path: Path | None = None):
     lib.pir_answer_multi.restype = ctypes.c_int
     lib.pir_answer_multi.argtypes = [ctypes.POINTER(PirTable), ctypes.c_uint32, ctypes.c_void_p,
                                      ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.pir_answer_bins.restype = ctypes.c_int
+    lib.pir_answer_bins.argtypes = [ctypes.c_uint32, ctypes.POINTER(PirBins), ctypes.c_uint32,
+                                    ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
     lib.pir_reconstruct.restype = ctypes.c_int
     lib.pir_reconstruct.argtypes = [u32p, u32p, ctypes.c_uint32, u32p]
     lib.pir_check_status.restype = ctypes.c_int
@@ -227,6 +236,53 @@ def answer_multi(tables, key_counts, keys, out=None, stream=None, prf=PRF_AES128
         n = int(c) * t.shape[1]
         views.append(out[off:off + n].view(int(c), t.shape[1]))
         off += n
+    return out, views
+
+
+def n_bins(rows: int, bin_log: int) -> int:
+    """Bins of 2^bin_log rows over a table of `rows` rows (the last may be shorter)."""
+    return (int(rows) + (1 << bin_log) - 1) >> bin_log
+
+
+def answer_bins(tables, client_counts, bin_logs, keys, out=None, stream=None, prf=PRF_AES128):
+    """Partial batch retrieval, server side (section 4.1), over one or more tables.
+
+    tables        : list of int32/uint32 device tensors [rows_t, dim_t] (dim_t <= 64)
+    client_counts : clients per table; each sends one key per bin of its table
+    bin_logs      : bins of 2^bin_logs[t] rows per table
+    keys          : uint8 device tensor, per table client-major: key (c, b) of
+                    table t is row sum_{t'<t} clients_t' bins_t' + c bins_t + b
+    Returns out and the list of per-table [clients_t, bins_t, dim_t] views.
+    """
+    import torch
+
+    lib = load()
+    _check_dev(keys, "keys", (torch.uint8,))
+    if not (len(tables) == len(client_counts) == len(bin_logs)):
+        raise ValueError("one client count and one bin size per table")
+    descs = (PirBins * max(1, len(tables)))()
+    total_keys, total = 0, 0
+    shapes = []
+    for i, (t, c, bl) in enumerate(zip(tables, client_counts, bin_logs)):
+        _check_dev(t, f"tables[{i}]", (torch.int32, torch.uint32))
+        nb = n_bins(t.shape[0], int(bl))
+        descs[i] = PirBins(t.data_ptr(), t.shape[0], t.shape[1], int(c), int(bl))
+        shapes.append((int(c), nb, t.shape[1]))
+        total_keys += int(c) * nb
+        total += int(c) * nb * t.shape[1]
+    if keys.shape[0] != total_keys:
+        raise ValueError(f"keys must hold {total_keys} rows (clients x bins per table)")
+    if out is None:
+        out = torch.empty(total, dtype=torch.int32, device=keys.device)
+    _check_dev(out, "out", (torch.int32, torch.uint32))
+    if out.numel() != total:
+        raise ValueError("out has the wrong size")
+    _check(lib.pir_answer_bins(prf_id(prf), descs, len(tables), keys.data_ptr(), keys.shape[1],
+                               out.data_ptr(), _stream_handle(stream)), "pir_answer_bins")
+    views, off = [], 0
+    for c, nb, d in shapes:
+        views.append(out[off:off + c * nb * d].view(c, nb, d))
+        off += c * nb * d
     return out, views
 
 

@@ -86,6 +86,12 @@ def zipf_indices(rows: int, count: int, seed: int, s: float = 1.05) -> np.ndarra
     return np.minimum(np.searchsorted(cdf, u, side="right"), rows - 1).astype(np.int64)
 
 
+def row_permutation(rows: int, seed: int) -> np.ndarray:
+    """A seeded permutation of [0, rows): maps popularity ranks to rows, so that
+    popular rows are scattered over the table instead of leading it."""
+    return np.random.default_rng([seed, 0x61]).permutation(rows).astype(np.int64)
+
+
 def key_seeds(count: int, seed: int) -> np.ndarray:
     """One 16-byte Gen seed per query, [count, 16] uint8."""
     rng = np.random.default_rng([seed, 0x31])

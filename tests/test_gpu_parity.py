@@ -342,3 +342,30 @@ def test_small_batches_sparse_full_size(O, pirmod, log_rows, dim, nkeys):
     assert (got == sparse_answers(O, keys, sup, vals)).all()
     del Ts
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("nkeys", [2, 16])
+def test_max_domain_2p32_rows(O, pirmod, nkeys):
+    """The largest table the ABI takes: 2^32 rows (n = 32) x 1 uint32, 16 GiB,
+    sparse; a key pair on the small-batch kernel and 16 keys on the wave
+    kernel, every per-server answer against the oracle's point evaluation and
+    the pairs reconstructing T[alpha]."""
+    import torch
+
+    rows, dim, seed = 1 << 32, 1, 32
+    Ts, sup, vals = make_sparse(rows, dim, seed, 16, "cuda")
+    pairs = nkeys // 2
+    alphas = W.uniform_indices(rows, pairs, seed + nkeys)
+    alphas[0] = sup[-1]  # the last row, 2^32 - 1 (make_sparse puts it in the support)
+    if pairs > 1:
+        alphas[1] = sup[7]
+    K0, K1 = oracle_keys(O, 32, alphas, seed + nkeys)
+    keys = np.concatenate([K0, K1])
+    got = gpu_answer(pirmod, keys, Ts)
+    assert (got == sparse_answers(O, keys, sup, vals)).all()
+    dense = {int(j): v for j, v in zip(sup, vals)}
+    for p in range(pairs):
+        r = ((got[p].astype(np.uint64) + got[pairs + p]) & 0xFFFFFFFF).astype(np.uint32)
+        assert (r == dense.get(int(alphas[p]), np.zeros(dim, np.uint32))).all(), p
+    del Ts
+    torch.cuda.empty_cache()

@@ -142,3 +142,59 @@ def test_answer_multi_validation_without_gpu(lib):
     assert lib.pir_answer_multi(T, 1, None, ks, None, None) == pir.PIR_OK
     assert lib.pir_answer_multi_prf(pir.PRF_CHACHA20, T, 1, None, ks, None, None) == pir.PIR_OK
     assert lib.pir_answer_multi_prf(5, T, 1, None, ks, None, None) == pir.PIR_EINVAL
+
+
+def test_answer_bins_validation_without_gpu(lib):
+    fake = 0x1000
+    ks = pir.key_size(10)
+    ok = pir.PirBins(fake, 1 << 14, 16, 4, 10)
+    bad = [
+        pir.PirBins(fake, 1 << 14, 65, 4, 10),      # rows wider than 64 words
+        pir.PirBins(fake, 1 << 14, 16, 4, 2),       # bins below 8 rows
+        pir.PirBins(fake, 0, 16, 4, 10),            # no rows
+        pir.PirBins(None, 1 << 14, 16, 4, 10),      # null table
+        pir.PirBins(fake, 1 << 14, 16, 4, 33),      # bins beyond 2^32 rows
+    ]
+    for d in bad:
+        T = (pir.PirBins * 2)(ok, d)
+        assert lib.pir_answer_bins(0, T, 2, fake, ks, fake, None) == pir.PIR_EINVAL, d.dim
+    T = (pir.PirBins * 1)(ok)
+    assert lib.pir_answer_bins(0, T, 1, fake, ks - 16, fake, None) == pir.PIR_EINVAL  # short stride
+    assert lib.pir_answer_bins(0, T, 1, 0x1008, ks, fake, None) == pir.PIR_EINVAL    # misaligned keys
+    assert lib.pir_answer_bins(7, T, 1, fake, ks, fake, None) == pir.PIR_EINVAL      # unknown PRF
+    T = (pir.PirBins * 1)(pir.PirBins(fake, 1 << 14, 16, 0, 10))
+    assert lib.pir_answer_bins(1, T, 1, None, ks, None, None) == pir.PIR_OK          # no clients
+
+
+def test_client_plans_match_the_oracle():
+    """The library's client plans (numpy) against the oracle's (plain loops)."""
+    from oracle import client as oc
+    from paper_2301_10904_amd import client as pc
+
+    rng = np.random.default_rng(31)
+    for trial in range(200):
+        rows = int(rng.integers(8, 3000))
+        bin_log = int(rng.integers(3, 12))
+        wanted = rng.integers(0, rows, int(rng.integers(0, 60)))
+        a, s, d = pc.pbr_plan(wanted, rows, bin_log)
+        oa, os_, od = oc.pbr_plan(wanted, rows, bin_log)
+        assert list(a) == oa and [None if x < 0 else int(x) for x in s] == os_ and list(d) == od
+        hot = rng.choice(rows, min(rows, 20), replace=False)
+        hot_of = np.full(rows, -1, np.int64)
+        hot_of[hot] = np.arange(hot.size)
+        q_hot, q_full = int(rng.integers(0, 6)), int(rng.integers(0, 6))
+        got = pc.hot_full_plan(wanted, hot_of, q_hot, q_full)
+        want = oc.hot_full_plan(wanted, {int(x): i for i, x in enumerate(hot)}, q_hot, q_full)
+        assert list(got[0]) == want[0] and list(got[1]) == want[1]
+        assert [None if x < 0 else int(x) for x in got[2]] == want[2]
+        assert [None if x < 0 else int(x) for x in got[3]] == want[3]
+        assert list(got[4]) == want[4]
+
+
+def test_hot_rows_by_frequency():
+    from paper_2301_10904_amd import client as pc
+
+    counts = np.array([5, 9, 9, 1, 0, 9, 9])
+    rows, hot_of = pc.hot_rows_by_frequency(counts, 3)
+    assert list(rows) == [1, 2, 5]
+    assert list(hot_of) == [-1, 0, 1, -1, -1, 2, -1]
