@@ -163,12 +163,14 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="keys of the workload the oracle answers for the CPU baseline (x8 for ChaCha20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", default="batch", choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull"],
+    ap.add_argument("--mode", default="batch",
+                    choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull", "sizes"],
                     help="batch: 2^20 x 64, 512 pairs (the default line); small: 2^14 x 16, one pair; "
                          "multi: 8 tables 2^16..2^23 x 32, ragged Zipf batches in one call; "
                          "large: 2^25 x 64 (8 GiB), 512..2048 pairs; serve: Poisson request loop over 4 tables; "
                          "pbr: partial batch retrieval on 2^20 x 64, bins of 2^10..2^14; "
-                         "hotfull: hot table + full table with fixed query budgets")
+                         "hotfull: hot table + full table with fixed query budgets; "
+                         "sizes: 2^14, 2^20, 2^22 rows x 64 (the table sizes of the paper's GPU/CPU comparison)")
     ap.add_argument("--prf", default="aes128", choices=["aes128", "chacha20"],
                     help="the DPF tree's PRF (section 3.2.6): AES-128 (default) or ChaCha20")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
@@ -412,11 +414,51 @@ def other_modes(args):
                     config={"workload": "one table 2^25 x 64 uint32 (8 GiB) resident, 1024/2048/4096 keys"})
     elif args.mode == "pbr":
         line.update(pbr_sweep(args))
+    elif args.mode == "sizes":
+        line.update(sizes_sweep(args))
     elif args.mode == "hotfull":
         line.update(hotfull_run(args))
     else:
         line.update(serve_sweep(args))
     print(json.dumps(line), flush=True)
+
+
+def sizes_sweep(args):
+    """Batched throughput and single-query latency at 2^14, 2^20 and 2^22 rows of
+    64 uint32 (2048-bit entries): the table sizes of the paper's comparison with
+    the CPU library (16K, 1M and 4M entries)."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    dim, runs, ok = 64, [], True
+    for n, pairs in ((14, 16384), (20, 512), (22, 128)):
+        rows, seed = 1 << n, 40 + n
+        T = W.make_table(rows, dim, seed, device=dev)
+        a = W.uniform_indices(rows, pairs, seed)
+        K0, K1 = pir.gen_batch(n, a, W.key_seeds(pairs, seed), prf=args.prf)
+        keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
+        out = torch.empty((2 * pairs, dim), dtype=torch.int32, device=dev)
+        sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=args.prf), 10, 2)
+        got = out.cpu().numpy().view(np.uint32)
+        rec = ((got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF).astype(np.uint32)
+        ok &= bool((rec == W.table_rows_np(a, dim, seed)).all())
+        k1 = keys[:1].contiguous()
+        o1 = torch.empty((1, dim), dtype=torch.int32, device=dev)
+        sec1, ms1 = time_launches(lambda: pir.answer(k1, T, o1, prf=args.prf), 50, 5)
+        runs.append({"rows": rows, "keys_per_call": 2 * pairs, "batched_ms": round(sec * 1e3, 3),
+                     "server_qps": round(2 * pairs / sec, 1),
+                     "single_query_p50_ms": round(percentile(ms1, 50), 4),
+                     "single_query_p99_ms": round(percentile(ms1, 99), 4),
+                     "single_query_qps": round(1 / sec1, 1)})
+        del T, keys, out
+        torch.cuda.empty_cache()
+    return {"value": runs[1]["server_qps"], "exact": ok, "sizes": runs,
+            "config": {"workload": "tables of 2^14, 2^20, 2^22 rows x 64 uint32, batches of 32768 / 1024 / 256 "
+                                   "keys (both servers), uniform alpha; one key for the single-query latency",
+                       "prf": args.prf}}
 
 
 def pbr_sweep(args):
