@@ -180,6 +180,27 @@ int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables
                     const uint8_t *d_keys, uint32_t key_stride, uint32_t *d_out,
                     void *stream);
 
+/* The work plan pir_answer / pir_answer_prf would use for one table (the
+ * batch scheduling of sections 3.2.1 and 3.2.5), for inspection and tests; it
+ * launches nothing and needs no GPU.  PIR_EINVAL for an unknown prf_id, no
+ * keys, or sizes pir_answer rejects; PIR_ENOMEM where pir_answer would. */
+#define PIR_KERNEL_WAVES 1       /* batched: 16 keys per wave, int8 matrix cores */
+#define PIR_KERNEL_SMALL_BATCH 2 /* 1..15 keys (or rows > 64 words): 512-lane workgroups */
+typedef struct {
+    uint32_t kernel;              /* PIR_KERNEL_* */
+    uint32_t n;                   /* key domain: ceil(log2 rows), at least 1 */
+    uint64_t items;               /* work items (waves or workgroups) */
+    uint64_t workgroups;          /* workgroups launched */
+    uint32_t lanes_per_workgroup;
+    uint32_t lds_bytes;           /* static LDS per workgroup */
+    uint32_t keys_per_item;       /* keys sharing one item's table rows */
+    uint32_t subtree_log;         /* each lane walks a subtree of 2^subtree_log leaves */
+    uint64_t rows_per_item;
+    uint32_t descent_levels;      /* tree levels walked from the root to an item's subtree */
+    uint32_t bfs_levels;          /* breadth-first levels in LDS (small-batch kernel) */
+} pir_plan_t;
+int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_plan_t *out);
+
 /* Client side reconstruction (paper section 3.1): out[k] = a0[k] + a1[k]
  * mod 2^32 for k < dim; host buffers.  PIR_EINVAL on null pointers. */
 int pir_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim, uint32_t *out);

@@ -1,0 +1,695 @@
+// pir_kernels.h -- device side of the fused full-domain DPF evaluation x table
+// product on gfx950: the PRF policies, the small-batch kernel k_pir_fused and
+// the batched kernel k_pir_waves, with the work-item structures their launchers
+// (pir_device.hip) fill in.  Included once, by pir_device.hip; everything here
+// has internal linkage.
+//
+// For every key q of a batch, one server computes (paper section 3.1)
+//     out[q][k] = sum_j Eval(k_q, j) * T[j][k]   (mod 2^32),
+// where Eval expands the key's GGM tree with the node recurrence of Eq.
+// (p1)-(p3): each internal node with seed s yields its two children
+// AES128_s(BE128(c)) ^ C_{t(s)}[c, d], c in {0,1}.
+//
+// Work decomposition (sections 3.2.1, 3.2.3 and 3.2.4 of the paper give the
+// V100 design: a batch over blocks, a depth-first traversal holding K nodes
+// per level, and the product fused at the leaves; here it is re-planned for
+// 64-wide wavefronts and a large LDS):
+//   * A work item is (group of Q keys, chunk of 2^H rows).  One workgroup of
+//     512 lanes owns an item: S = 512/Q lanes per key.
+//   * Descent: Q lanes walk from each root to the chunk's subtree root.
+//   * Breadth-first expansion in LDS until every lane holds one node.
+//   * Each lane then walks its own subtree of height h depth-first with the
+//     path (both children of every node on it) in registers: every node is
+//     evaluated once and no seed below the lane's root ever leaves the VGPRs.
+//   * Each step of that walk yields two leaf shares per lane; they go to LDS
+//     and the workgroup immediately multiplies them into the streamed table
+//     rows (coalesced: one wave reads one 256-byte row per instruction).
+//   * Partial sums are reduced across waves in LDS and added with 32-bit
+//     atomics into out; integer addition mod 2^32 makes the result exact and
+//     independent of the order.
+//
+// AES-128 (aes_gfx950.h) runs on little-endian column words with the combined
+// SubBytes/MixColumns tables replicated per lane in LDS, so table lookups never
+// conflict; the tables fill the first 64 KiB, and two workgroups share a CU.
+// Keys with the ChaCha20 PRF (chacha_gfx950.h, section 3.2.6) run the same
+// kernels instantiated with a register-only PRF and no table in LDS.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "aes_gfx950.h"
+#include "aes_tables.h"
+#include "chacha_gfx950.h"
+#include "pir.h"
+
+namespace {
+
+using namespace pir_dev;
+
+constexpr int NT = 512;      // lanes per workgroup
+constexpr int NW = NT / 64;  // waves per workgroup
+constexpr int HMAX = 10;     // largest per-lane subtree height
+constexpr int QMAX = 16;     // keys per workgroup
+
+__constant__ pir_aes::Words256 c_TE = pir_aes::TE;
+__device__ uint32_t g_key_error;
+
+struct Seed {
+    uint32_t w[4];
+};
+
+// The PRF of a launch.  Each provides both children's PRF outputs of a node,
+// one child's, and word 0 of both (all a leaf share needs); TAB_WORDS is the
+// LDS table it reads (filled by fill()), 0 for none.
+struct AesPrf {
+    static constexpr uint32_t id = PIR_PRF_AES128;
+    static constexpr uint32_t TAB_WORDS = AES_TAB_WORDS;
+    Lanes L;
+    __device__ __forceinline__ AesPrf(const uint32_t *tab, uint32_t lane) : L(tab, lane) {}
+    static __device__ __forceinline__ void fill(uint32_t *tab, uint32_t tid, uint32_t nt)
+    {
+        fill_tables(tab, c_TE.v, tid, nt);
+    }
+    __device__ __forceinline__ void pair(const uint32_t s[4], uint32_t a[4], uint32_t b[4]) const
+    {
+        prf_pair(s, a, b, L);
+    }
+    __device__ __forceinline__ void one(const uint32_t s[4], uint32_t c, uint32_t a[4]) const { prf_one(s, c, a, L); }
+    __device__ __forceinline__ void pair_word0(const uint32_t s[4], uint32_t &y0, uint32_t &y1) const
+    {
+        prf_pair_word0(s, y0, y1, L);
+    }
+};
+
+struct ChaChaPrf {
+    static constexpr uint32_t id = PIR_PRF_CHACHA20;
+    static constexpr uint32_t TAB_WORDS = 0;
+    __device__ __forceinline__ ChaChaPrf(const uint32_t *, uint32_t) {}
+    static __device__ __forceinline__ void fill(uint32_t *, uint32_t, uint32_t) {}
+    __device__ __forceinline__ void pair(const uint32_t s[4], uint32_t a[4], uint32_t b[4]) const
+    {
+        chacha_pair(s, a, b);
+    }
+    __device__ __forceinline__ void one(const uint32_t s[4], uint32_t c, uint32_t a[4]) const { chacha_one(s, c, a); }
+    __device__ __forceinline__ void pair_word0(const uint32_t s[4], uint32_t &y0, uint32_t &y1) const
+    {
+        chacha_pair_word0(s, y0, y1);
+    }
+};
+
+// The whole LDS of a workgroup: the PRF's table (if any), which is reused for
+// the cross-wave sums of up to QMAX x PIR_MAX_DIM words.
+template <uint32_t TABW>
+struct Smem {
+    static constexpr uint32_t W = TABW > QMAX * PIR_MAX_DIM ? TABW : QMAX * PIR_MAX_DIM;
+    uint32_t tab[W];
+    union {
+        Seed bfs[NT];              // breadth-first nodes
+        uint32_t sh[2 * NT];       // leaf shares of one walk step: [2 S][Q]
+    } u;
+    uint32_t keyok[QMAX];          // 0 = skip, 1 = party 0, 2 = party 1
+};
+
+struct KeyView {
+    const uint8_t *p; // key base (16-byte aligned)
+    __device__ __forceinline__ Seed root() const
+    {
+        uint4 v = *reinterpret_cast<const uint4 *>(p + 16);
+        return Seed{{v.x, v.y, v.z, v.w}};
+    }
+    // C_t[0, d] and C_t[1, d]
+    __device__ __forceinline__ void cw(uint32_t d, uint32_t t, uint4 &c0, uint4 &c1) const
+    {
+        const uint4 *q = reinterpret_cast<const uint4 *>(p + 32 + 64 * (size_t)(d - 1) + 32 * t);
+        c0 = q[0];
+        c1 = q[1];
+    }
+    __device__ __forceinline__ uint2 cw_word0(uint32_t d, uint32_t t) const
+    {
+        const uint32_t *q = reinterpret_cast<const uint32_t *>(p + 32 + 64 * (size_t)(d - 1) + 32 * t);
+        return make_uint2(q[0], q[4]);
+    }
+};
+
+// Both children of the node with seed s, codeword level d (Eq. (p3)).
+template <class PRF>
+__device__ __forceinline__ void children(const PRF &P, const KeyView &K, const Seed &s, uint32_t d, Seed &c0,
+                                         Seed &c1)
+{
+    uint4 w0, w1;
+    K.cw(d, s.w[0] & 1u, w0, w1);
+    uint32_t a[4], b[4];
+    P.pair(s.w, a, b);
+    c0 = Seed{{a[0] ^ w0.x, a[1] ^ w0.y, a[2] ^ w0.z, a[3] ^ w0.w}};
+    c1 = Seed{{b[0] ^ w1.x, b[1] ^ w1.y, b[2] ^ w1.z, b[3] ^ w1.w}};
+}
+
+// Child c of the node with seed s, codeword level d (Eq. (p3)), for descents.
+template <class PRF>
+__device__ __forceinline__ Seed child_on_path(const PRF &P, const KeyView &K, const Seed &s, uint32_t d, uint32_t c)
+{
+    const uint4 *q = reinterpret_cast<const uint4 *>(K.p + 32 + 64 * (size_t)(d - 1) + 32 * (s.w[0] & 1u) + 16 * c);
+    const uint4 w = *q;
+    uint32_t a[4];
+    P.one(s.w, c, a);
+    return Seed{{a[0] ^ w.x, a[1] ^ w.y, a[2] ^ w.z, a[3] ^ w.w}};
+}
+
+// Logical block index of this workgroup.  The hardware deals workgroups to the
+// 8 XCDs in turn (block b to XCD b mod 8), and each XCD has its own L2; work
+// items that read the same table rows sit at consecutive logical indices, so
+// the map gives every XCD one contiguous range of logical blocks (a bijection
+// on [0, gridDim.x)) and rows shared by neighbouring blocks stay in one L2.
+__device__ __forceinline__ uint32_t xcd_block()
+{
+    constexpr uint32_t XCDS = 8;
+    const uint32_t nb = gridDim.x, b = blockIdx.x;
+    const uint32_t x = b % XCDS, k = b / XCDS, per = nb / XCDS, extra = nb % XCDS;
+    return x * per + (x < extra ? x : extra) + k;
+}
+
+__global__ void k_fill_zero(uint32_t *out, size_t count)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < count; i += stride)
+        out[i] = 0;
+}
+
+struct Geometry {
+    uint32_t n;        // log2 of the key domain
+    uint32_t H;        // rows per item = 2^H
+    uint32_t lgS;      // lanes used per key = 2^lgS (lgS < H)
+    uint32_t n_groups; // key groups of Q
+    uint32_t n_chunks; // row chunks
+};
+
+// Q keys per group (Q <= QMAX); KCH column chunks of 64 (dim <= 64 KCH);
+// VEC4: dim is a multiple of 4 (16-byte row segments are aligned).
+template <class PRF, int Q, int KCH, bool VEC4>
+__global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ keys, uint32_t n_keys,
+                                                  uint32_t stride, const uint32_t *__restrict__ table,
+                                                  uint64_t rows, uint32_t dim, uint32_t *__restrict__ out,
+                                                  Geometry g)
+{
+    constexpr int S = NT / Q;
+    __shared__ Smem<PRF::TAB_WORDS> sm;
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63, wave = tid >> 6;
+    const uint32_t blk = xcd_block();
+    const uint32_t grp = blk % g.n_groups;
+    const uint32_t chunk = blk / g.n_groups;
+    const uint64_t row_base = (uint64_t)chunk << g.H;
+    const PRF P(sm.tab, lane);
+
+    PRF::fill(sm.tab, tid, NT);
+
+    // key headers; roots of the keys
+    const uint32_t dtop = g.n - g.H;
+    if (tid < Q) {
+        const uint32_t kq = grp * Q + tid;
+        uint32_t ok = 0;
+        Seed s{{0, 0, 0, 0}};
+        if (kq < n_keys) {
+            const KeyView K{keys + (size_t)kq * stride};
+            const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
+            const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
+            ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == PRF::id) ? 1u + party : 0u;
+            if (!ok)
+                atomicOr(&g_key_error, 1u);
+            else
+                s = K.root();
+        }
+        sm.keyok[tid] = ok;
+        sm.u.bfs[tid] = s;
+    }
+    __syncthreads(); // tables and roots are in place
+
+    // descent from each root to the chunk's subtree root at depth n - H
+    if (tid < Q && sm.keyok[tid]) {
+        const KeyView K{keys + (size_t)(grp * Q + tid) * stride};
+        Seed s = sm.u.bfs[tid];
+        for (uint32_t d = 1; d <= dtop; d++)
+            s = child_on_path(P, K, s, d, (uint32_t)(row_base >> (g.n - d)) & 1u);
+        sm.u.bfs[tid] = s;
+    }
+    __syncthreads();
+
+    // breadth-first expansion in LDS, in place: Q * 2^lgS nodes at depth dtop + lgS
+    for (uint32_t l = 1; l <= g.lgS; l++) {
+        const uint32_t half = 1u << (l - 1);
+        const bool mine = tid < Q * half;
+        const uint32_t q = tid >> (l - 1), j = tid & (half - 1);
+        Seed c0{{0, 0, 0, 0}}, c1{{0, 0, 0, 0}};
+        if (mine && sm.keyok[q]) {
+            const KeyView K{keys + (size_t)(grp * Q + q) * stride};
+            children(P, K, sm.u.bfs[tid], dtop + l, c0, c1);
+        }
+        __syncthreads(); // every parent has been read
+        if (mine) {
+            sm.u.bfs[q * 2 * half + 2 * j] = c0;
+            sm.u.bfs[q * 2 * half + 2 * j + 1] = c1;
+        }
+        __syncthreads();
+    }
+
+    // per-lane depth-first walk of a subtree of height h
+    const uint32_t q = tid / S, ln = tid % S;
+    const uint32_t S_used = 1u << g.lgS;
+    const bool active = ln < S_used && sm.keyok[q];
+    const uint32_t h = g.H - g.lgS;       // >= 1
+    const uint32_t d0 = g.n - h;          // depth of the lane's root
+    const uint32_t steps = 1u << (h - 1); // bottom nodes per lane
+    const KeyView K{keys + (size_t)(grp * Q + q) * stride};
+    Seed node = active ? sm.u.bfs[q * S_used + ln] : Seed{{0, 0, 0, 0}};
+    const Seed root = node;
+    Seed right[HMAX];
+#pragma unroll
+    for (int i = 0; i < HMAX; i++)
+        right[i] = Seed{{0, 0, 0, 0}};
+
+    // WIDE: few accumulators per column; a lane then owns 4 columns of one of
+    // 4 row slots, otherwise one column of every row
+    constexpr bool WIDE = Q * KCH <= 4;
+    uint32_t acc[WIDE ? 1 : Q][WIDE ? 1 : KCH];
+    uint32_t accw[WIDE ? Q : 1][WIDE ? KCH : 1][4];
+#pragma unroll
+    for (int i = 0; i < (WIDE ? 1 : Q); i++)
+#pragma unroll
+        for (int c = 0; c < (WIDE ? 1 : KCH); c++)
+            acc[i][c] = 0;
+#pragma unroll
+    for (int i = 0; i < (WIDE ? Q : 1); i++)
+#pragma unroll
+        for (int c = 0; c < (WIDE ? KCH : 1); c++)
+#pragma unroll
+            for (int e = 0; e < 4; e++)
+                accw[i][c][e] = 0;
+
+    uint32_t(*sh)[Q] = reinterpret_cast<uint32_t(*)[Q]>(sm.u.sh);
+    for (uint32_t m = 0; m < steps; m++) {
+        uint32_t kst;
+        if (m == 0) {
+            node = root;
+            kst = 1;
+        } else {
+            const uint32_t kf = h - 1 - __builtin_ctz(m);
+#pragma unroll
+            for (int i = 1; i < HMAX; i++)
+                if ((uint32_t)i == kf)
+                    node = right[i];
+            kst = kf + 1;
+        }
+        uint32_t y0 = 0, y1 = 0;
+        if (active) {
+            for (uint32_t k = kst; k < h; k++) {
+                Seed c0, c1;
+                children(P, K, node, d0 + k, c0, c1);
+#pragma unroll
+                for (int i = 1; i < HMAX; i++)
+                    if ((uint32_t)i == k)
+                        right[i] = c1;
+                node = c0;
+            }
+            const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
+            P.pair_word0(node.w, y0, y1);
+            y0 ^= cw.x;
+            y1 ^= cw.y;
+        }
+        __syncthreads(); // the previous step's readers are done with sh (and the roots were read)
+        if (ln < S_used) {
+            sh[2 * ln][q] = y0;
+            sh[2 * ln + 1][q] = y1;
+        }
+        __syncthreads();
+        const uint32_t n_rows = 2 * S_used;
+        if (WIDE) {
+            // lane = (row slot rs = lane / 16, column group cg = lane mod 16):
+            // one 16-byte load covers 4 columns, a wave covers 4 rows per
+            // load, and U loads are in flight before any is used
+            constexpr int U = KCH >= 4 ? 1 : 4 / KCH;
+            const uint32_t rs = lane >> 4, cg = lane & 15;
+            for (uint32_t i0 = wave * 4; i0 < n_rows; i0 += NW * 4 * U) {
+                uint32_t tv[U][KCH][4];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const uint32_t i = i0 + u * NW * 4 + rs;
+                    const uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
+                    const bool ok = i < n_rows && row < rows;
+                    const uint32_t *trow = table + (ok ? row : 0) * dim;
+#pragma unroll
+                    for (int c = 0; c < KCH; c++) {
+                        const uint32_t col = 64 * c + 4 * cg;
+                        if (VEC4) {
+                            const uint4 x = col < dim ? *reinterpret_cast<const uint4 *>(trow + col) : make_uint4(0, 0, 0, 0);
+                            tv[u][c][0] = ok ? x.x : 0u;
+                            tv[u][c][1] = ok ? x.y : 0u;
+                            tv[u][c][2] = ok ? x.z : 0u;
+                            tv[u][c][3] = ok ? x.w : 0u;
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                const uint32_t cc = col + e;
+                                const uint32_t x = trow[cc < dim ? cc : dim - 1];
+                                tv[u][c][e] = (ok && cc < dim) ? x : 0u;
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const uint32_t i = i0 + u * NW * 4 + rs;
+                    const uint32_t ii = i < n_rows ? i : 0; // masked rows add zero
+#pragma unroll
+                    for (int qq = 0; qq < Q; qq++) {
+                        const uint32_t y = sh[ii][qq];
+#pragma unroll
+                        for (int c = 0; c < KCH; c++)
+#pragma unroll
+                            for (int e = 0; e < 4; e++)
+                                accw[qq][c][e] += y * tv[u][c][e];
+                    }
+                }
+            }
+        } else {
+            // lane = column: U rows per round, their words loaded together
+            // (clamped addresses, masked values) so the loads overlap
+            constexpr int U = (Q * KCH >= 32) ? 2 : (Q * KCH >= 8 ? 4 : 8);
+            for (uint32_t i0 = wave; i0 < n_rows; i0 += NW * U) {
+                uint32_t tv[U][KCH];
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const uint32_t i = i0 + u * NW;
+                    const uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
+                    const bool ok = i < n_rows && row < rows;
+                    const uint32_t *trow = table + (ok ? row : 0) * dim;
+#pragma unroll
+                    for (int c = 0; c < KCH; c++) {
+                        const uint32_t col = lane + 64 * c;
+                        const uint32_t x = trow[col < dim ? col : dim - 1];
+                        tv[u][c] = (ok && col < dim) ? x : 0u;
+                    }
+                }
+#pragma unroll
+                for (int u = 0; u < U; u++) {
+                    const uint32_t i = i0 + u * NW;
+                    const uint32_t ii = i < n_rows ? i : 0;
+#pragma unroll
+                    for (int qq = 0; qq < Q; qq++) {
+                        const uint32_t y = sh[ii][qq];
+#pragma unroll
+                        for (int c = 0; c < KCH; c++)
+                            acc[qq][c] += y * tv[u][c];
+                    }
+                }
+            }
+        }
+    }
+
+    // reduce the waves' partial sums in LDS (the tables are no longer needed)
+    __syncthreads();
+    uint32_t *s_acc = sm.tab;
+    for (uint32_t i = tid; i < Q * dim; i += NT)
+        s_acc[i] = 0;
+    __syncthreads();
+    if (WIDE) {
+#pragma unroll
+        for (int qq = 0; qq < (WIDE ? Q : 1); qq++)
+#pragma unroll
+            for (int c = 0; c < (WIDE ? KCH : 1); c++)
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t col = 64 * c + 4 * (lane & 15) + e;
+                    if (col < dim)
+                        atomicAdd(&s_acc[qq * dim + col], accw[qq][c][e]);
+                }
+    } else {
+#pragma unroll
+        for (int qq = 0; qq < (WIDE ? 1 : Q); qq++)
+#pragma unroll
+            for (int c = 0; c < (WIDE ? 1 : KCH); c++) {
+                const uint32_t col = lane + 64 * c;
+                if (col < dim)
+                    atomicAdd(&s_acc[qq * dim + col], acc[qq][c]);
+            }
+    }
+    __syncthreads();
+    for (uint32_t i = tid; i < Q * dim; i += NT) {
+        const uint32_t qq = i / dim, col = i % dim;
+        const uint32_t ok = sm.keyok[qq];
+        if (!ok)
+            continue;
+        uint32_t v = s_acc[i];
+        if (ok == 2)
+            v = 0u - v; // party 1 holds the negated share
+        atomicAdd(&out[(size_t)(grp * Q + qq) * dim + col], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched kernel: every wave is an independent work item, and the share x
+// table product runs on the int8 matrix cores.
+//
+// A wave item is (16 keys, chunk of 4 * 2^h rows).  Lane l evaluates key
+// (l mod 16) over subtree (l / 16) of the chunk: it walks from the key's root
+// to the subtree root itself (n - h nodes, so no lane waits for another), then
+// depth-first over the subtree with the path in registers.  Each walk step
+// gives a lane the shares of two consecutive rows, so the 64 lanes together
+// hold an [16 keys x 8 rows] share tile, exactly the A operand layout of
+// v_mfma_i32_16x16x32_i8 (lane l: row l mod 16, K slice (l / 16) * 8 .. +7).
+//
+// Exactness mod 2^32 on int8 units: a uint32 x has balanced base-256 digits
+// d_0..d_3 in [-128, 127] with x = sum d_a 256^a (mod 2^32); they are the bytes
+// of (x + 0x80808080) ^ 0x80808080.  Then
+//     y * T = sum_{s=0..3} 256^s * sum_{a+b=s} d_a(y) e_b(T)      (mod 2^32),
+// so for each s one MFMA with A = digits of y arranged d_s, d_{s-1}, .., d_0
+// and B = digits of T gives the s-th term; the int32 accumulators wrap mod 2^32.
+// Each step folds its four terms into one running sum per tile.
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+constexpr int NW3 = 8;             // waves per workgroup (two workgroups per CU)
+constexpr int HMAX3 = 9;           // largest per-lane subtree height of the wave kernel
+constexpr int NT3 = 64 * NW3;
+
+__device__ __forceinline__ uint32_t balanced(uint32_t x) { return (x + 0x80808080u) ^ 0x80808080u; }
+
+// digits of x arranged for shift s: byte j holds d_{s-j} (0 where j > s)
+template <int S>
+__device__ __forceinline__ uint32_t arrange(uint32_t x)
+{
+    if (S == 0)
+        return x & 0xffu;
+    constexpr uint32_t sel = S == 1 ? 0x0c0c0001u : S == 2 ? 0x0c000102u : 0x00010203u;
+    return __builtin_amdgcn_perm(x, x, sel);
+}
+
+__device__ __forceinline__ long pack2(uint32_t lo, uint32_t hi) { return (long)(((uint64_t)hi << 32) | lo); }
+
+// KT consecutive words T[r][c0 .. c0 + KT - 1] (zero outside the table).
+// VEC: dim == 16 KT, so the words are in bounds and 4 KT-byte aligned.
+template <int KT, bool VEC>
+__device__ __forceinline__ void load_cols(const uint32_t *__restrict__ table, uint64_t r, uint64_t rows, uint32_t dim,
+                                          uint32_t c0, uint32_t (&v)[KT])
+{
+    const bool row_ok = r < rows;
+    const uint32_t *p = table + (row_ok ? r : rows - 1) * dim;
+    if (VEC) {
+        if (KT == 4) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(p + c0);
+            v[0] = x.x;
+            v[KT > 1 ? 1 : 0] = x.y;
+            v[KT > 2 ? 2 : 0] = x.z;
+            v[KT > 3 ? 3 : 0] = x.w;
+        } else if (KT == 2) {
+            const uint2 x = *reinterpret_cast<const uint2 *>(p + c0);
+            v[0] = x.x;
+            v[KT > 1 ? 1 : 0] = x.y;
+        } else {
+            v[0] = p[c0];
+        }
+#pragma unroll
+        for (int t = 0; t < KT; t++)
+            v[t] = row_ok ? v[t] : 0u;
+    } else {
+#pragma unroll
+        for (int t = 0; t < KT; t++) {
+            const uint32_t c = c0 + t;
+            const uint32_t x = p[c < dim ? c : dim - 1];
+            v[t] = (row_ok && c < dim) ? x : 0u;
+        }
+    }
+}
+
+// One table's share of a wave-kernel launch.  The table is cut into n_bins
+// bins of 2^n rows (the last may be shorter; one bin for a whole-table query)
+// and every client sends one key per bin: key (c, b) at keys + (c n_bins + b)
+// * stride, answer at out + (c n_bins + b) * dim.
+struct WaveTask {
+    const uint32_t *table; // row-major uint32 [rows][dim]
+    const uint8_t *keys;   // this table's first key
+    uint32_t *out;         // this table's first answer word
+    uint64_t rows;
+    uint32_t dim, n_keys, n, h, n_groups, item_begin;
+    uint32_t n_bins, chunks_per_bin; // n_keys counts clients
+};
+constexpr int MAX_TASKS = 16;
+struct WaveTasks {
+    WaveTask t[MAX_TASKS];
+    uint32_t count, n_items;
+};
+
+template <class PRF, int KT, bool VEC>
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_waves(const WaveTasks tasks,
+                                                                                           uint32_t stride)
+{
+    __shared__ uint32_t tab[PRF::TAB_WORDS ? PRF::TAB_WORDS : 1];
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const PRF P(tab, lane);
+    if (PRF::TAB_WORDS) {
+        PRF::fill(tab, tid, NT3);
+        __syncthreads();
+    }
+
+    const uint32_t item0 = xcd_block() * NW3 + wave;
+    if (item0 >= tasks.n_items)
+        return; // whole wave; no barrier follows
+    uint32_t ti = 0; // the table this item belongs to (tasks are in item order)
+    while (ti + 1 < tasks.count && item0 >= tasks.t[ti + 1].item_begin)
+        ti++;
+    const WaveTask &g = tasks.t[ti];
+    const uint32_t item = item0 - g.item_begin;
+    const uint32_t dim = g.dim, n_keys = g.n_keys;
+    const uint32_t grp = item % g.n_groups, bin_chunk = item / g.n_groups;
+    const uint32_t bin = bin_chunk / g.chunks_per_bin, chunk = bin_chunk % g.chunks_per_bin;
+    // this bin's rows, keys (one per client, n_bins apart) and answers
+    const uint64_t first_row = (uint64_t)bin << g.n;
+    const uint64_t rows_left = g.rows - first_row;
+    const uint64_t rows = rows_left < ((uint64_t)1 << g.n) ? rows_left : ((uint64_t)1 << g.n);
+    const uint32_t *__restrict__ table = g.table + first_row * dim;
+    const uint8_t *__restrict__ keys = g.keys + (size_t)bin * stride;
+    uint32_t *__restrict__ out = g.out + (size_t)bin * dim;
+    const size_t key_step = (size_t)g.n_bins * stride, out_step = (size_t)g.n_bins * dim;
+    const uint32_t q = lane & 15, sub = lane >> 4;
+    const uint32_t kq = grp * 16 + q;
+    const uint32_t h = g.h;
+
+    uint32_t ok = 0;
+    const KeyView K{keys + (size_t)(kq < n_keys ? kq : 0) * key_step};
+    if (kq < n_keys) {
+        const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
+        const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
+        ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == PRF::id) ? 1u + party : 0u;
+        if (!ok && sub == 0)
+            atomicOr(&g_key_error, 1u);
+    }
+    const uint64_t lane_row0 = ((uint64_t)chunk * 4 + sub) << h;
+    const bool active = ok && lane_row0 < rows;
+
+    // walk from the root to this lane's subtree root (depth n - h)
+    Seed node{{0, 0, 0, 0}};
+    if (active) {
+        node = K.root();
+        for (uint32_t d = 1; d + h <= g.n; d++)
+            node = child_on_path(P, K, node, d, (uint32_t)(lane_row0 >> (g.n - d)) & 1u);
+    }
+    const uint32_t d0 = g.n - h;
+    Seed right[HMAX3];
+#pragma unroll
+    for (int i = 0; i < HMAX3; i++)
+        right[i] = Seed{{0, 0, 0, 0}};
+
+    // running sum over steps of sum_s 256^s D_s, per tile (wraps mod 2^32)
+    v4i tot[KT];
+#pragma unroll
+    for (int t = 0; t < KT; t++)
+        tot[t] = v4i{0, 0, 0, 0};
+
+    // this lane's table columns: tile t, column n = lane mod 16 -> n * KT + t
+    const uint32_t col0 = (lane & 15) * KT;
+    const uint32_t steps = 1u << (h - 1);
+    for (uint32_t m = 0; m < steps; m++) {
+        // table words of the two rows this lane feeds to the product; issued
+        // first and unconditionally (clamped addresses, masked values), so
+        // their latency hides behind this step's AES work
+        const uint64_t r0 = lane_row0 + 2 * m;
+        uint32_t t0[KT], t1[KT];
+        load_cols<KT, VEC>(table, r0, rows, dim, col0, t0);
+        load_cols<KT, VEC>(table, r0 + 1, rows, dim, col0, t1);
+
+        uint32_t kst = 1; // step 0 starts at the lane's root, already in `node`
+        if (m != 0) {
+            const uint32_t kf = h - 1 - __builtin_ctz(m);
+#pragma unroll
+            for (int i = 1; i < HMAX3; i++)
+                if ((uint32_t)i == kf)
+                    node = right[i];
+            kst = kf + 1;
+        }
+        uint32_t y0 = 0, y1 = 0;
+        if (active) {
+            for (uint32_t k = kst; k < h; k++) {
+                Seed c0, c1;
+                children(P, K, node, d0 + k, c0, c1);
+#pragma unroll
+                for (int i = 1; i < HMAX3; i++)
+                    if ((uint32_t)i == k)
+                        right[i] = c1;
+                node = c0;
+            }
+            const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
+            P.pair_word0(node.w, y0, y1);
+            y0 ^= cw.x;
+            y1 ^= cw.y;
+        }
+
+        const uint32_t e0 = balanced(y0), e1 = balanced(y1);
+        const long a0 = pack2(arrange<0>(e0), arrange<0>(e1));
+        const long a1 = pack2(arrange<1>(e0), arrange<1>(e1));
+        const long a2 = pack2(arrange<2>(e0), arrange<2>(e1));
+        const long a3 = pack2(arrange<3>(e0), arrange<3>(e1));
+        const v4i zero = {0, 0, 0, 0};
+#pragma unroll
+        for (int t = 0; t < KT; t++) {
+            // tot += D_0 + 2^8 (D_1 + 2^8 (D_2 + 2^8 D_3)): D_0 accumulates in
+            // the matrix core, the rest is three shift-and-add steps per word
+            const long b = pack2(balanced(t0[t]), balanced(t1[t]));
+            const v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b, zero, 0, 0, 0);
+            const v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a2, b, zero, 0, 0, 0);
+            const v4i c3 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3, b, zero, 0, 0, 0);
+            v4i acc = tot[t];
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                // the empty asm keeps each (x << 8) + y a single v_lshl_add_u32
+                // (the compiler would otherwise expand the chain into separate shifts)
+                uint32_t hi = ((uint32_t)c3[i] << 8) + (uint32_t)c2[i];
+                asm volatile("" : "+v"(hi));
+                hi = (hi << 8) + (uint32_t)c1[i];
+                asm volatile("" : "+v"(hi));
+                acc[i] = (int)((uint32_t)acc[i] + (hi << 8));
+            }
+            tot[t] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b, acc, 0, 0, 0);
+        }
+    }
+
+    // lane l holds D[(l / 16) * 4 + i][l mod 16] of every (shift, tile)
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t key = (lane >> 4) * 4 + i;
+        const uint32_t kok = __shfl(ok, (int)key);
+        if (!kok)
+            continue;
+#pragma unroll
+        for (int t = 0; t < KT; t++) {
+            const uint32_t col = col0 + t;
+            if (col >= dim)
+                continue;
+            uint32_t v = (uint32_t)tot[t][i];
+            if (kok == 2)
+                v = 0u - v;
+            atomicAdd(&out[(size_t)(grp * 16 + key) * out_step + col], v);
+        }
+    }
+}
+
+} // namespace

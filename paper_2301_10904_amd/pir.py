@@ -22,8 +22,9 @@ PRFS = {"aes128": PRF_AES128, "chacha20": PRF_CHACHA20}
 
 # the exported C ABI, as declared in include/pir.h
 EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_prf",
-           "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_reconstruct",
+           "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_plan", "pir_reconstruct",
            "pir_check_status", "pir_strerror", "pir_last_hip_error")
+KERNEL_WAVES, KERNEL_SMALL_BATCH = 1, 2
 BINS_MIN_LOG, BINS_MAX_DIM = 3, 64
 
 _lib = None
@@ -39,6 +40,14 @@ class PirError(RuntimeError):
 class PirTable(ctypes.Structure):
     _fields_ = [("d_table", ctypes.c_void_p), ("rows", ctypes.c_uint64),
                 ("dim", ctypes.c_uint32), ("n_keys", ctypes.c_uint32)]
+
+
+class PirPlan(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_uint32), ("n", ctypes.c_uint32), ("items", ctypes.c_uint64),
+                ("workgroups", ctypes.c_uint64), ("lanes_per_workgroup", ctypes.c_uint32),
+                ("lds_bytes", ctypes.c_uint32), ("keys_per_item", ctypes.c_uint32),
+                ("subtree_log", ctypes.c_uint32), ("rows_per_item", ctypes.c_uint64),
+                ("descent_levels", ctypes.c_uint32), ("bfs_levels", ctypes.c_uint32)]
 
 
 class PirBins(ctypes.Structure):
@@ -82,6 +91,9 @@ def load(path: Path | None = None):
     lib.pir_answer_bins.restype = ctypes.c_int
     lib.pir_answer_bins.argtypes = [ctypes.c_uint32, ctypes.POINTER(PirBins), ctypes.c_uint32,
                                     ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    lib.pir_plan.restype = ctypes.c_int
+    lib.pir_plan.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
+                             ctypes.POINTER(PirPlan)]
     lib.pir_reconstruct.restype = ctypes.c_int
     lib.pir_reconstruct.argtypes = [u32p, u32p, ctypes.c_uint32, u32p]
     lib.pir_check_status.restype = ctypes.c_int
@@ -237,6 +249,13 @@ def answer_multi(tables, key_counts, keys, out=None, stream=None, prf=PRF_AES128
         views.append(out[off:off + n].view(int(c), t.shape[1]))
         off += n
     return out, views
+
+
+def plan(n_keys: int, rows: int, dim: int, prf=PRF_AES128) -> dict:
+    """The work plan pir_answer uses for one table (no GPU needed)."""
+    p = PirPlan()
+    _check(load().pir_plan(prf_id(prf), n_keys, rows, dim, ctypes.byref(p)), "pir_plan")
+    return {name: getattr(p, name) for name, _ in PirPlan._fields_}
 
 
 def n_bins(rows: int, bin_log: int) -> int:

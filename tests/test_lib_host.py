@@ -198,3 +198,69 @@ def test_hot_rows_by_frequency():
     rows, hot_of = pc.hot_rows_by_frequency(counts, 3)
     assert list(rows) == [1, 2, 5]
     assert list(hot_of) == [-1, 0, 1, -1, -1, 2, -1]
+
+
+def test_plan_batched_default_workload():
+    p = pir.plan(1024, 1 << 20, 64)
+    assert p["kernel"] == pir.KERNEL_WAVES and p["n"] == 20
+    assert p["subtree_log"] == 9 and p["descent_levels"] == 11 and p["bfs_levels"] == 0
+    assert p["keys_per_item"] == 16 and p["rows_per_item"] == 4 << 9
+    assert p["items"] == 64 * ((1 << 20) // (4 << 9))  # 64 key groups x 512 row chunks
+    assert p["workgroups"] == p["items"] // 8 and p["lanes_per_workgroup"] == 512
+    assert p["lds_bytes"] == 65536
+    assert pir.plan(1024, 1 << 20, 64, prf="chacha20")["lds_bytes"] == 0
+
+
+def test_plan_single_key_spreads_over_every_cu():
+    """One key on 2^20 rows: the small-batch kernel with about two workgroups
+    per CU of the 256, each covering its own rows."""
+    for rows in (1 << 20, 1 << 22, 1 << 25, 1 << 32):
+        p = pir.plan(1, rows, 64)
+        assert p["kernel"] == pir.KERNEL_SMALL_BATCH
+        assert p["workgroups"] >= 2 * 256, (rows, p)
+        assert p["workgroups"] * p["rows_per_item"] >= rows
+        assert p["descent_levels"] + p["bfs_levels"] + p["subtree_log"] == p["n"]
+
+
+def test_plan_small_wave_batches_fill_the_gpu():
+    """16 keys: one key group, so the subtree height drops until there are at
+    least 8192 wave items (about eight per wave slot of the GPU)."""
+    p = pir.plan(16, 1 << 20, 64)
+    assert p["kernel"] == pir.KERNEL_WAVES
+    assert p["items"] >= 8192 and p["subtree_log"] == 5
+    assert p["descent_levels"] + p["subtree_log"] == 20
+
+
+def test_plan_kernel_choice():
+    assert pir.plan(1024, 1 << 20, 65)["kernel"] == pir.KERNEL_SMALL_BATCH   # rows wider than 64 words
+    assert pir.plan(15, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH     # fewer than 16 keys
+    assert pir.plan(64, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH            # n = 2: too small for waves
+    assert pir.plan(64, 8, 8)["kernel"] == pir.KERNEL_WAVES                  # n = 3
+    rng = np.random.default_rng(5)
+    for _ in range(300):
+        keys = int(rng.integers(1, 5000))
+        rows = int(rng.integers(1, 1 << int(rng.integers(1, 33))))
+        dim = int(rng.integers(1, 257))
+        p = pir.plan(keys, rows, dim)
+        n = max(1, (rows - 1).bit_length())
+        assert p["n"] == n
+        if p["kernel"] == pir.KERNEL_WAVES:
+            assert keys >= 16 and dim <= 64 and n >= 3
+            assert p["descent_levels"] + p["subtree_log"] == n
+            chunks = -(-rows // p["rows_per_item"])
+            assert p["items"] == chunks * -(-keys // 16)
+        else:
+            assert p["descent_levels"] + p["bfs_levels"] + p["subtree_log"] == n
+            chunks = -(-rows // p["rows_per_item"])
+            assert p["workgroups"] == chunks * -(-keys // p["keys_per_item"])
+            assert p["items"] == p["workgroups"]
+            assert 1 <= p["subtree_log"] <= 10
+
+
+def test_plan_rejects_bad_arguments(lib):
+    out = pir.PirPlan()
+    assert lib.pir_plan(0, 1, 1 << 10, 8, ctypes.byref(out)) == pir.PIR_OK
+    for args in ((2, 1, 1 << 10, 8), (0, 0, 1 << 10, 8), (0, 1, 0, 8), (0, 1, 1 << 10, 0),
+                 (0, 1, 1 << 10, 257), (0, 1, (1 << 32) + 1, 8)):
+        assert lib.pir_plan(*args, ctypes.byref(out)) == pir.PIR_EINVAL, args
+    assert lib.pir_plan(0, 1, 1 << 10, 8, None) == pir.PIR_EINVAL
