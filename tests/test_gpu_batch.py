@@ -144,3 +144,57 @@ def test_hot_full_two_tables_one_call(O, pirmod):
             assert (hot[c * q_hot + i] == (T[x] if x is not None else H[0])).all()
         for i, x in enumerate(sf):
             assert (full[c * q_full + i] == (T[x] if x is not None else T[0])).all()
+
+
+def test_answer_multi_many_tables(O, pirmod):
+    """41 tables of every column class in one call (more than a launch takes,
+    so several launches per class), some without keys, small and wave-kernel
+    batches mixed: every per-server answer bit-exact."""
+    import torch
+
+    rng = np.random.default_rng(41)
+    dims = [1, 5, 16, 17, 32, 33, 64, 70, 130, 256]
+    tables, counts, keysets, expect = [], [], [], []
+    for t in range(41):
+        rows = int(rng.integers(2, 3000))
+        dim = dims[t % len(dims)]
+        n = max(1, (rows - 1).bit_length())
+        T = W.make_table(rows, dim, 300 + t)
+        tables.append(T.cuda())
+        nk = int(rng.choice([0, 1, 3, 16, 21]))
+        counts.append(nk)
+        if nk == 0:
+            expect.append(None)
+            continue
+        K, _ = O.gen_batch(n, W.uniform_indices(rows, nk, 300 + t), W.key_seeds(nk, 300 + t))
+        keysets.append(K)
+        expect.append(O.answer_batch(K, T.numpy().view(np.uint32), nthreads=cpu_threads()))
+    stride = (max(k.shape[1] for k in keysets) + 15) // 16 * 16
+    keys = np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keysets])
+    _, views = pirmod.answer_multi(tables, counts, torch.from_numpy(keys).cuda())
+    torch.cuda.synchronize()
+    for t, (v, e) in enumerate(zip(views, expect)):
+        if e is not None:
+            assert (v.cpu().numpy().view(np.uint32) == e).all(), t
+
+
+def test_bins_bad_key_header(O, pirmod):
+    """A binned key with a wrong domain or PRF id answers zero and raises the
+    key flag; the other keys of the call are unaffected."""
+    rows, dim, bin_log, clients, seed = 1000, 8, 7, 2, 44
+    T = W.make_table(rows, dim, seed).numpy().view(np.uint32)
+    alphas = random_alphas(rows, bin_log, clients, seed)
+    K0, _ = oracle_bin_keys(O, alphas, bin_log, seed)
+    K0[3, 2] = bin_log + 1   # wrong domain
+    K0[10, 3] = 1            # ChaCha20 id in an AES call
+    assert pirmod.check_status() == pirmod.PIR_OK
+    (got,) = run_bins(pirmod, [T], [K0], [clients], [bin_log], 0)
+    assert pirmod.check_status() == pirmod.PIR_EKEY
+    flat = got.reshape(-1, dim)
+    assert (flat[3] == 0).all() and (flat[10] == 0).all()
+    good = [i for i in range(len(K0)) if i not in (3, 10)]
+    nb = -(-rows // (1 << bin_log))
+    for i in good:
+        c, b = divmod(i, nb)
+        want = O.answer(K0[i], T[b << bin_log:(b + 1) << bin_log])
+        assert (flat[i] == want).all(), i
