@@ -62,7 +62,8 @@ LOOKUPS_FULL_NODE, LOOKUPS_BOTTOM_NODE = LOOKUPS_NODE["aes128"]
 PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x VALU lanes per clock x clock: 39.3 T int32 op/s
 PEAK_LDS_LOOKUPS = 256 * 32 * 2.4e9  # CUs x 128 B/clk of LDS reads / 4 B: 19.7 T lookups/s
 KERNEL_SOURCES = ["paper_2301_10904_amd/csrc/pir_kernels.h", "paper_2301_10904_amd/csrc/aes_gfx950.h",
-                  "paper_2301_10904_amd/csrc/aes_tables.h", "paper_2301_10904_amd/csrc/chacha_gfx950.h"]
+                  "paper_2301_10904_amd/csrc/aes_tables.h", "paper_2301_10904_amd/csrc/chacha_gfx950.h",
+                  "paper_2301_10904_amd/csrc/quad_gfx950.h"]
 TRAFFIC_SUMMARY = {"aes128": ROOT / "profiles" / "k_pir_waves_2p20x64_b1024_traffic.json",
                    "chacha20": ROOT / "profiles" / "k_pir_waves_chacha20_2p20x64_b1024_traffic.json"}
 

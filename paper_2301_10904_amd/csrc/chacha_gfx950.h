@@ -17,6 +17,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "quad_gfx950.h"
+
 namespace pir_dev {
 
 // "expand 32-byte k" as four little-endian words
@@ -95,6 +97,40 @@ __device__ __forceinline__ void chacha_pair_word0(const uint32_t s[4], uint32_t 
     chacha_rounds(s, x);
     y0 = x[0] + CHACHA_C0;
     y1 = x[4] + s[0];
+}
+
+// Quad form (quad_gfx950.h): lane q of the quad holds column q of the state,
+// words q, 4 + q, 8 + q, 12 + q, which start as the constant word q, the seed
+// word q (twice) and zero -- the lane's own seed word is all it needs.  The
+// column round is one quarter round per lane with no exchange; for the
+// diagonal round lane q takes word 4 + (q+1) mod 4, 8 + (q+2) mod 4 and
+// 12 + (q+3) mod 4 from its neighbours and gives them back afterwards.  At the
+// end lane q holds word q of PRF_s(0) and word q of PRF_s(1) (state word 4 + q).
+__device__ __forceinline__ void quad_chacha_pair(uint32_t s, uint32_t &a, uint32_t &b, const Quad &Q)
+{
+    const uint32_t cw[4] = {CHACHA_C0, CHACHA_C1, CHACHA_C2, CHACHA_C3};
+    const uint32_t c = Q.own(cw);
+    uint32_t xa = c, xb = s, xc = s, xd = 0u;
+#pragma unroll
+    for (int r = 0; r < 10; r++) {
+        quarter(xa, xb, xc, xd);
+        xb = quad_next<1>(xb);
+        xc = quad_next<2>(xc);
+        xd = quad_next<3>(xd);
+        quarter(xa, xb, xc, xd);
+        xb = quad_next<3>(xb);
+        xc = quad_next<2>(xc);
+        xd = quad_next<1>(xd);
+    }
+    a = xa + c;
+    b = xb + s;
+}
+
+__device__ __forceinline__ uint32_t quad_chacha_one(uint32_t s, uint32_t c, const Quad &Q)
+{
+    uint32_t a, b;
+    quad_chacha_pair(s, a, b, Q);
+    return c ? b : a;
 }
 
 } // namespace pir_dev

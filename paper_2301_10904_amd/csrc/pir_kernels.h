@@ -60,9 +60,12 @@ struct Seed {
 // The PRF of a launch.  Each provides both children's PRF outputs of a node,
 // one child's, and word 0 of both (all a leaf share needs); TAB_WORDS is the
 // LDS table it reads (filled by fill()), 0 for none.
+// QUAD: the PRF also has the quad form (four lanes per node, lane q holding
+// word q), used where a walk is latency-bound.
 struct AesPrf {
     static constexpr uint32_t id = PIR_PRF_AES128;
     static constexpr uint32_t TAB_WORDS = AES_TAB_WORDS;
+    static constexpr bool QUAD = true;
     Lanes L;
     __device__ __forceinline__ AesPrf(const uint32_t *tab, uint32_t lane) : L(tab, lane) {}
     static __device__ __forceinline__ void fill(uint32_t *tab, uint32_t tid, uint32_t nt)
@@ -78,11 +81,28 @@ struct AesPrf {
     {
         prf_pair_word0(s, y0, y1, L);
     }
+    __device__ __forceinline__ void quad_pair(uint32_t s, uint32_t &a, uint32_t &b, const Quad &Qd) const
+    {
+        quad_prf_pair(s, a, b, Qd, L);
+    }
+    __device__ __forceinline__ uint32_t quad_one(uint32_t s, uint32_t c, const Quad &Qd) const
+    {
+        return quad_prf_one(s, c, Qd, L);
+    }
 };
 
 struct ChaChaPrf {
     static constexpr uint32_t id = PIR_PRF_CHACHA20;
     static constexpr uint32_t TAB_WORDS = 0;
+    static constexpr bool QUAD = true;
+    __device__ __forceinline__ void quad_pair(uint32_t s, uint32_t &a, uint32_t &b, const Quad &Qd) const
+    {
+        quad_chacha_pair(s, a, b, Qd);
+    }
+    __device__ __forceinline__ uint32_t quad_one(uint32_t s, uint32_t c, const Quad &Qd) const
+    {
+        return quad_chacha_one(s, c, Qd);
+    }
     __device__ __forceinline__ ChaChaPrf(const uint32_t *, uint32_t) {}
     static __device__ __forceinline__ void fill(uint32_t *, uint32_t, uint32_t) {}
     __device__ __forceinline__ void pair(const uint32_t s[4], uint32_t a[4], uint32_t b[4]) const
@@ -225,8 +245,25 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     }
     __syncthreads(); // tables and roots are in place
 
-    // descent from each root to the chunk's subtree root at depth n - H
-    if (tid < Q && sm.keyok[tid]) {
+    // descent from each root to the chunk's subtree root at depth n - H: a
+    // dependent chain, walked by a quad of lanes per key where the PRF has the
+    // quad form (lane w holds word w of the seed)
+    const Quad Qd(lane);
+    if constexpr (PRF::QUAD) {
+        const uint32_t qk = tid >> 2, w = tid & 3;
+        if (tid < 4 * Q && sm.keyok[qk]) { // whole quads: qk is the same for the four lanes
+            const KeyView K{keys + (size_t)(grp * Q + qk) * stride};
+            uint32_t s = sm.u.bfs[qk].w[w];
+            for (uint32_t d = 1; d <= dtop; d++) {
+                const uint32_t c = (uint32_t)(row_base >> (g.n - d)) & 1u;
+                const uint32_t t = quad_first(s) & 1u;
+                const uint32_t cw = *reinterpret_cast<const uint32_t *>(K.p + 32 + 64 * (size_t)(d - 1) + 32 * t +
+                                                                        16 * c + 4 * w);
+                s = P.quad_one(s, c, Qd) ^ cw;
+            }
+            sm.u.bfs[qk].w[w] = s;
+        }
+    } else if (tid < Q && sm.keyok[tid]) {
         const KeyView K{keys + (size_t)(grp * Q + tid) * stride};
         Seed s = sm.u.bfs[tid];
         for (uint32_t d = 1; d <= dtop; d++)
@@ -238,6 +275,31 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     // breadth-first expansion in LDS, in place: Q * 2^lgS nodes at depth dtop + lgS
     for (uint32_t l = 1; l <= g.lgS; l++) {
         const uint32_t half = 1u << (l - 1);
+        if (PRF::QUAD && 4 * Q * half <= NT) {
+            // a quad of lanes per node while the level is narrow
+            const uint32_t nd = tid >> 2, w = tid & 3;
+            const bool mine = nd < Q * half; // whole quads
+            const uint32_t q = nd >> (l - 1), j = nd & (half - 1);
+            uint32_t c0 = 0, c1 = 0;
+            if (mine && sm.keyok[q]) {
+                const KeyView K{keys + (size_t)(grp * Q + q) * stride};
+                const uint32_t s = sm.u.bfs[nd].w[w];
+                const uint32_t t = quad_first(s) & 1u;
+                const uint32_t *cwp =
+                    reinterpret_cast<const uint32_t *>(K.p + 32 + 64 * (size_t)(dtop + l - 1) + 32 * t);
+                uint32_t a, b;
+                P.quad_pair(s, a, b, Qd);
+                c0 = a ^ cwp[w];
+                c1 = b ^ cwp[4 + w];
+            }
+            __syncthreads(); // every parent has been read
+            if (mine) {
+                sm.u.bfs[q * 2 * half + 2 * j].w[w] = c0;
+                sm.u.bfs[q * 2 * half + 2 * j + 1].w[w] = c1;
+            }
+            __syncthreads();
+            continue;
+        }
         const bool mine = tid < Q * half;
         const uint32_t q = tid >> (l - 1), j = tid & (half - 1);
         Seed c0{{0, 0, 0, 0}}, c1{{0, 0, 0, 0}};
