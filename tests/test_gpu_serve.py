@@ -17,7 +17,8 @@ from paper_2301_10904_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-def test_serve_poisson_four_tables(gpu_lib):
+@pytest.mark.parametrize("prf", ["aes128", "chacha20"])
+def test_serve_poisson_four_tables(gpu_lib, prf):
     import torch
 
     from paper_2301_10904_amd import pir
@@ -25,13 +26,13 @@ def test_serve_poisson_four_tables(gpu_lib):
 
     logs = [10, 12, 14, 20]
     total = sum((1 << lg) * 32 * 4 for lg in logs)  # a 128 MiB table among them
-    srv = PirServer(hbm_budget_bytes=total, max_batch=256, max_queue=512, max_inflight=2)
+    srv = PirServer(hbm_budget_bytes=total, max_batch=256, max_queue=512, max_inflight=2, prf=prf)
     pool, alphas = [], []
     for i, lg in enumerate(logs):
         T = W.make_table(1 << lg, 32, 60 + i, device="cuda")
         assert srv.admit_table(T) == i
         a = W.uniform_indices(1 << lg, 64, 60 + i)
-        K0, K1 = pir.gen_batch(lg, a, W.key_seeds(64, 60 + i))
+        K0, K1 = pir.gen_batch(lg, a, W.key_seeds(64, 60 + i), prf=prf)
         pool.append(np.concatenate([K0, K1]))
         alphas.append(np.concatenate([a, a]))
     # the budget is exhausted: one more table is refused
@@ -43,7 +44,7 @@ def test_serve_poisson_four_tables(gpu_lib):
     def check(t, ki, row):
         partner = ki + 64 if ki < 64 else ki - 64
         pk = torch.from_numpy(pool[t][partner:partner + 1]).cuda()
-        other = pir.answer(pk, srv.tables[t][0]).cpu().numpy().view(np.uint32)[0]
+        other = pir.answer(pk, srv.tables[t][0], prf=prf).cpu().numpy().view(np.uint32)[0]
         want = W.table_rows_np([alphas[t][ki]], 32, 60 + t)[0]
         checked.append(bool((pir.reconstruct(row, other) == want).all()))
 
