@@ -165,13 +165,14 @@ def main():
                     help="keys of the workload the oracle answers for the CPU baseline (x8 for ChaCha20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--mode", default="batch",
-                    choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull", "sizes"],
+                    choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull", "sizes", "batchsweep"],
                     help="batch: 2^20 x 64, 512 pairs (the default line); small: 2^14 x 16, one pair; "
                          "multi: 8 tables 2^16..2^23 x 32, ragged Zipf batches in one call; "
                          "large: 2^25 x 64 (8 GiB), 512..2048 pairs; serve: Poisson request loop over 4 tables; "
                          "pbr: partial batch retrieval on 2^20 x 64, bins of 2^10..2^14; "
                          "hotfull: hot table + full table with fixed query budgets; "
-                         "sizes: 2^14, 2^20, 2^22 rows x 64 (the table sizes of the paper's GPU/CPU comparison)")
+                         "sizes: 2^14, 2^20, 2^22 rows x 64 (the table sizes of the paper's GPU/CPU comparison); "
+                         "batchsweep: latency and throughput for 1..1024 keys per call on 2^20 x 64")
     ap.add_argument("--prf", default="aes128", choices=["aes128", "chacha20"],
                     help="the DPF tree's PRF (section 3.2.6): AES-128 (default) or ChaCha20")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
@@ -417,11 +418,53 @@ def other_modes(args):
         line.update(pbr_sweep(args))
     elif args.mode == "sizes":
         line.update(sizes_sweep(args))
+    elif args.mode == "batchsweep":
+        line.update(batch_sweep(args))
     elif args.mode == "hotfull":
         line.update(hotfull_run(args))
     else:
         line.update(serve_sweep(args))
     print(json.dumps(line), flush=True)
+
+
+def batch_sweep(args):
+    """Latency (p50/p99 per call) and server throughput against the number of
+    keys per call on one 2^20 x 64 table: the batch-size trade-off of the
+    paper's evaluation."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    rows, dim, seed = 1 << 20, 64, 77
+    T = W.make_table(rows, dim, seed, device=dev)
+    a = W.uniform_indices(rows, 512, seed)
+    K0, K1 = pir.gen_batch(20, a, W.key_seeds(512, seed), prf=args.prf)
+    allk = torch.from_numpy(np.concatenate([K0, K1])).to(dev)  # key i pairs with key 512 + i
+    want = W.table_rows_np(a, dim, seed)
+    runs, ok = [], True
+    for B in (1, 2, 4, 8, 9, 12, 15, 16, 17, 24, 32, 64, 128, 256, 512, 1024):
+        if B == 1:
+            keys = allk[:1].contiguous()
+        else:
+            half = B // 2
+            keys = torch.cat([allk[:half], allk[512:512 + half]] + ([allk[half:half + 1]] if B % 2 else [])).contiguous()
+        out = torch.empty((keys.shape[0], dim), dtype=torch.int32, device=dev)
+        steps = 50 if B <= 64 else 10
+        sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=args.prf), steps, 3)
+        if B >= 2:
+            got = out.cpu().numpy().view(np.uint32)
+            half = B // 2
+            rec = ((got[:half].astype(np.uint64) + got[half:2 * half]) & 0xFFFFFFFF).astype(np.uint32)
+            ok &= bool((rec == want[:half]).all())
+        plan = pir.plan(B, rows, dim, prf=args.prf)
+        runs.append({"keys": B, "kernel": "waves" if plan["kernel"] == pir.KERNEL_WAVES else "small_batch",
+                     "p50_ms": round(percentile(ms, 50), 4), "p99_ms": round(percentile(ms, 99), 4),
+                     "server_qps": round(B / sec, 1)})
+    return {"value": runs[-1]["server_qps"], "exact": ok, "batchsweep": runs,
+            "config": {"workload": "one table 2^20 x 64 uint32, 1..1024 keys per call (both servers' keys), "
+                                   "uniform alpha", "prf": args.prf}}
 
 
 def sizes_sweep(args):

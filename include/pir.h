@@ -184,8 +184,8 @@ int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables
  * batch scheduling of sections 3.2.1 and 3.2.5), for inspection and tests; it
  * launches nothing and needs no GPU.  PIR_EINVAL for an unknown prf_id, no
  * keys, or sizes pir_answer rejects; PIR_ENOMEM where pir_answer would. */
-#define PIR_KERNEL_WAVES 1       /* batched: 16 keys per wave, int8 matrix cores */
-#define PIR_KERNEL_SMALL_BATCH 2 /* 1..15 keys (or rows > 64 words): 512-lane workgroups */
+#define PIR_KERNEL_WAVES 1       /* batched: up to 16 keys per wave, int8 matrix cores */
+#define PIR_KERNEL_SMALL_BATCH 2 /* small batches (or rows > 64 words): 512-lane workgroups */
 typedef struct {
     uint32_t kernel;              /* PIR_KERNEL_* */
     uint32_t n;                   /* key domain: ceil(log2 rows), at least 1 */

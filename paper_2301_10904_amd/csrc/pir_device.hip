@@ -55,13 +55,41 @@ static int fail_hip(hipError_t e)
     return PIR_EHIP;
 }
 
+constexpr uint64_t WAVE_SLOTS = 256 * 16; // waves resident at once: 256 CUs x two 8-wave workgroups
+
+// Subtree height of a single-table wave launch.  A lane's work per item is its
+// descent (n - h single-block nodes, a dependent chain that runs at about half
+// the rate of the walk, so weighted 2) plus the 2^h - 1 nodes of its subtree;
+// the launch takes about max(items, slots) / slots rounds of that, and a
+// launch of at most one round pays about 10% for its unfilled tail.  Small
+// batches have few key groups, so a lower h gives more items but a relatively
+// longer descent; the model picks the balance (measured: 16 keys on 2^20 rows
+// 0.84 -> 0.61 ms against a fixed minimum of 8192 items).
+static uint32_t wave_height(uint64_t n_bins, uint64_t bin_rows, uint64_t groups, uint32_t n, uint32_t hmax)
+{
+    uint32_t best_h = hmax;
+    double best = 0.0;
+    for (uint32_t h = hmax; h >= 3 && h <= hmax; h--) {
+        const uint64_t chunks = (bin_rows + ((uint64_t)4 << h) - 1) / ((uint64_t)4 << h);
+        const uint64_t items = n_bins * chunks * groups;
+        const double per_lane = 2.0 * (double)(n - h) + (double)((1u << h) - 1);
+        const double t = per_lane * (double)std::max<uint64_t>(items, WAVE_SLOTS) / (double)WAVE_SLOTS *
+                         (items <= WAVE_SLOTS ? 1.1 : 1.0);
+        if (h == hmax || t < best) {
+            best = t;
+            best_h = h;
+        }
+    }
+    return best_h;
+}
+
 // Work plan of a wave-kernel launch over `count` tasks: fills h, n_groups,
 // chunks_per_bin and item_begin of every task and returns the number of wave
-// items (0 if it reaches 2^31).  The subtree height h is as large as the path
-// registers allow (HMAX3, and n - 2 so that a bin holds four subtrees); for a
-// single table it is lowered until there are at least min_items items, so
-// that small batches still fill every CU several times.
-static uint64_t plan_waves(WaveTask *ts, uint32_t count, uint64_t min_items)
+// items (0 if it reaches 2^31).  The subtree height h is at most what the path
+// registers allow (HMAX3) and n - 2 (a bin holds four subtrees); a single
+// table gets the height of wave_height(), a launch of several tables the
+// largest (the tables together fill the GPU).
+static uint64_t plan_waves(WaveTask *ts, uint32_t count)
 {
     uint64_t items = 0;
     for (uint32_t i = 0; i < count; i++) {
@@ -69,9 +97,8 @@ static uint64_t plan_waves(WaveTask *ts, uint32_t count, uint64_t min_items)
         t.n_groups = (t.n_keys + 15) / 16;
         const uint64_t bin_rows = std::min<uint64_t>(t.rows, (uint64_t)1 << t.n);
         auto chunks_per_bin = [&](uint32_t hh) { return (bin_rows + ((uint64_t)4 << hh) - 1) / ((uint64_t)4 << hh); };
-        uint32_t h = std::min<uint32_t>(HMAX3, t.n - 2);
-        while (count == 1 && h > 3 && (uint64_t)t.n_bins * chunks_per_bin(h) * t.n_groups < min_items)
-            h--;
+        const uint32_t hmax = std::min<uint32_t>(HMAX3, t.n - 2);
+        const uint32_t h = count == 1 ? wave_height(t.n_bins, bin_rows, t.n_groups, t.n, hmax) : hmax;
         t.h = h;
         t.chunks_per_bin = (uint32_t)chunks_per_bin(h);
         t.item_begin = (uint32_t)items;
@@ -82,18 +109,16 @@ static uint64_t plan_waves(WaveTask *ts, uint32_t count, uint64_t min_items)
     return items;
 }
 
-constexpr uint64_t MIN_WAVE_ITEMS = 8192; // about 8 items per wave slot of the GPU
-
 // Wave-kernel launch for up to MAX_TASKS tables of one column class (KT, VEC).
 // Plans the tasks and clears their outputs first.
 template <class PRF>
-static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipStream_t st, uint64_t min_items)
+static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipStream_t st)
 {
     WaveTasks W;
     bool any = false;
     for (uint32_t i = 0; i < count; i++)
         any |= ts[i].n_keys > 0;
-    const uint64_t items = plan_waves(ts, count, min_items);
+    const uint64_t items = plan_waves(ts, count);
     if (items == 0 && any)
         return PIR_ENOMEM;
     for (uint32_t i = 0; i < count; i++)
@@ -139,10 +164,17 @@ static int wave_class(uint32_t dim)
     return -1;
 }
 
-// Which kernel answers one table: the wave kernel (int8 matrix cores, 16 keys
-// per wave) once there are 16 keys to share its row tiles, else the
-// small-batch kernel, which also takes rows wider than 64 words.
-static bool use_wave_kernel(uint32_t n_keys, uint32_t n, uint32_t dim) { return n_keys >= 16 && n >= 3 && dim <= 64; }
+// Which kernel answers one table: the wave kernel (int8 matrix cores, up to 16
+// keys per wave) from a PRF-dependent batch size on, else the small-batch
+// kernel, which also takes rows wider than 64 words.  A wave item costs the
+// same for 9..16 keys; measured on 2^20 x 64 rows it beats the small-batch
+// kernel from 9 keys with AES-128 (0.62 against 0.69 ms at 15 keys) but only
+// from 17 with ChaCha20 (0.59 against 0.66 ms at 16 keys).
+static uint32_t wave_min_keys(uint32_t prf_id) { return prf_id == PIR_PRF_CHACHA20 ? 17u : 9u; }
+static bool use_wave_kernel(uint32_t prf_id, uint32_t n_keys, uint32_t n, uint32_t dim)
+{
+    return n_keys >= wave_min_keys(prf_id) && n >= 3 && dim <= 64;
+}
 
 // Work plan of the small-batch kernel: Q keys per workgroup, chunks of 2^H
 // rows, breadth-first expansion to 2^lgS lanes per key, per-lane subtrees of
@@ -192,7 +224,7 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
         ((uintptr_t)d_table % 4) || ((uintptr_t)d_out % 4))
         return PIR_EINVAL;
 
-    if (use_wave_kernel(n_keys, n, dim)) {
+    if (use_wave_kernel(PRF::id, n_keys, n, dim)) {
         WaveTask t;
         t.table = d_table;
         t.keys = d_keys;
@@ -202,7 +234,7 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
         t.n_keys = n_keys;
         t.n = n;
         t.n_bins = 1;
-        return launch_waves<PRF>(&t, 1, key_stride, st, MIN_WAVE_ITEMS);
+        return launch_waves<PRF>(&t, 1, key_stride, st);
     }
 
     const FusedPlan p = plan_fused(n_keys, rows, dim, n);
@@ -279,7 +311,7 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
     for (auto &v : cls)
         for (size_t i = 0; i < v.size(); i += MAX_TASKS) {
             const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, v.size() - i);
-            int st = launch_waves<PRF>(v.data() + i, cnt, key_stride, (hipStream_t)stream, MIN_WAVE_ITEMS);
+            int st = launch_waves<PRF>(v.data() + i, cnt, key_stride, (hipStream_t)stream);
             if (st != PIR_OK)
                 return st;
         }
@@ -331,7 +363,7 @@ static int answer_bins(const pir_bins_t *tables, uint32_t n_tables, const uint8_
     for (auto &v : cls)
         for (size_t i = 0; i < v.size(); i += MAX_TASKS) {
             const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, v.size() - i);
-            int st = launch_waves<PRF>(v.data() + i, cnt, key_stride, (hipStream_t)stream, MIN_WAVE_ITEMS);
+            int st = launch_waves<PRF>(v.data() + i, cnt, key_stride, (hipStream_t)stream);
             if (st != PIR_OK)
                 return st;
         }
@@ -351,14 +383,14 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
     const bool aes = prf_id == PIR_PRF_AES128;
     *out = pir_plan_t{};
     out->n = n;
-    if (use_wave_kernel(n_keys, n, dim)) {
+    if (use_wave_kernel(prf_id, n_keys, n, dim)) {
         WaveTask t{};
         t.rows = rows;
         t.dim = dim;
         t.n_keys = n_keys;
         t.n = n;
         t.n_bins = 1;
-        const uint64_t items = plan_waves(&t, 1, MIN_WAVE_ITEMS);
+        const uint64_t items = plan_waves(&t, 1);
         if (items == 0)
             return PIR_ENOMEM;
         out->kernel = PIR_KERNEL_WAVES;

@@ -223,17 +223,28 @@ def test_plan_single_key_spreads_over_every_cu():
 
 
 def test_plan_small_wave_batches_fill_the_gpu():
-    """16 keys: one key group, so the subtree height drops until there are at
-    least 8192 wave items (about eight per wave slot of the GPU)."""
+    """Few key groups: the subtree height drops below the register limit (9)
+    until the items fill the GPU's 4096 wave slots, but not so far that the
+    per-lane descent dominates; many groups keep the full height."""
     p = pir.plan(16, 1 << 20, 64)
     assert p["kernel"] == pir.KERNEL_WAVES
-    assert p["items"] >= 8192 and p["subtree_log"] == 5
+    assert p["items"] == 4096 and p["subtree_log"] == 6
     assert p["descent_levels"] + p["subtree_log"] == 20
+    assert pir.plan(64, 1 << 20, 64)["subtree_log"] == 7
+    assert pir.plan(128, 1 << 20, 64)["subtree_log"] == 8
+    for keys in (256, 1024, 4096):
+        assert pir.plan(keys, 1 << 20, 64)["subtree_log"] == 9
+    for keys in (16, 17, 31, 40, 100, 300, 5000):
+        p = pir.plan(keys, 1 << 20, 64)
+        assert p["items"] >= 4096 and 3 <= p["subtree_log"] <= 9, (keys, p)
 
 
 def test_plan_kernel_choice():
     assert pir.plan(1024, 1 << 20, 65)["kernel"] == pir.KERNEL_SMALL_BATCH   # rows wider than 64 words
-    assert pir.plan(15, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH     # fewer than 16 keys
+    assert pir.plan(8, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH      # up to 8 keys (AES-128)
+    assert pir.plan(9, 1 << 20, 64)["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(16, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH  # ChaCha20: 16
+    assert pir.plan(17, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(64, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH            # n = 2: too small for waves
     assert pir.plan(64, 8, 8)["kernel"] == pir.KERNEL_WAVES                  # n = 3
     rng = np.random.default_rng(5)
@@ -245,7 +256,7 @@ def test_plan_kernel_choice():
         n = max(1, (rows - 1).bit_length())
         assert p["n"] == n
         if p["kernel"] == pir.KERNEL_WAVES:
-            assert keys >= 16 and dim <= 64 and n >= 3
+            assert keys >= 9 and dim <= 64 and n >= 3
             assert p["descent_levels"] + p["subtree_log"] == n
             chunks = -(-rows // p["rows_per_item"])
             assert p["items"] == chunks * -(-keys // 16)
