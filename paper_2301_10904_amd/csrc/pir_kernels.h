@@ -348,8 +348,25 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             for (int e = 0; e < 4; e++)
                 accw[i][c][e] = 0;
 
+    // Several keys share every row of the chunk, so the workgroup gathers the
+    // shares of all keys for a row before the row is read (two barriers per
+    // step).  With one key every row belongs to exactly one lane's subtree:
+    // each wave then multiplies the rows of its own lanes' leaves and needs
+    // no other wave, so the waves drift apart and the tree work of some
+    // overlaps the table stream of others.  In that case lane (rs, cg) =
+    // (lane / 16, lane mod 16) reads 16-byte column group cg of wave-row
+    // r = 4 k + rs, k = 0..31, which is leaf r mod 2 of the step in the
+    // subtree of lane r / 2; the shares go through a wave-private LDS slot as
+    // shw[r mod 4][r / 4], rows padded to 36 words so that the four row slots
+    // fall in different banks.
     uint32_t(*sh)[Q] = reinterpret_cast<uint32_t(*)[Q]>(sm.u.sh);
-    for (uint32_t m = 0; m < steps; m++) {
+    constexpr uint32_t SHP = 36;
+    uint32_t *shw = reinterpret_cast<uint32_t *>(sm.u.bfs) + wave * 4 * SHP;
+    const uint32_t lane0 = wave * 64;
+    if (Q == 1)
+        __syncthreads(); // every lane has read its node: the breadth-first area is free
+    const uint32_t n_steps = (Q == 1 && lane0 >= S_used) ? 0u : steps; // a wave with no lane in use
+    for (uint32_t m = 0; m < n_steps; m++) {
         uint32_t kst;
         if (m == 0) {
             node = root;
@@ -377,6 +394,57 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             P.pair_word0(node.w, y0, y1);
             y0 ^= cw.x;
             y1 ^= cw.y;
+        }
+        if constexpr (Q == 1) {
+            // the previous step's reads of the slot come first in this wave's LDS order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            shw[(2 * (lane & 1)) * SHP + (lane >> 1)] = y0;
+            shw[(2 * (lane & 1) + 1) * SHP + (lane >> 1)] = y1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            constexpr uint32_t U = KCH >= 4 ? 2 : 8 / KCH;
+            const uint32_t rs = lane >> 4, cg = lane & 15;
+#pragma unroll 1 // one group of U rows in flight per wave; more costs occupancy
+            for (uint32_t k0 = 0; k0 < 32; k0 += U) {
+                uint32_t tv[U][KCH][4], yv[U];
+#pragma unroll
+                for (int u = 0; u < (int)U; u++) {
+                    const uint32_t k = k0 + u, j = lane0 + 2 * k + (rs >> 1);
+                    const uint64_t row = row_base + ((uint64_t)j << h) + 2 * m + (rs & 1);
+                    const bool ok = j < S_used && row < rows;
+                    const uint32_t *trow = table + (ok ? row : 0) * dim;
+#pragma unroll
+                    for (int c = 0; c < KCH; c++) {
+                        const uint32_t col = 64 * c + 4 * cg;
+                        if (VEC4) {
+                            const uint4 x =
+                                col < dim ? *reinterpret_cast<const uint4 *>(trow + col) : make_uint4(0, 0, 0, 0);
+                            tv[u][c][0] = ok ? x.x : 0u;
+                            tv[u][c][1] = ok ? x.y : 0u;
+                            tv[u][c][2] = ok ? x.z : 0u;
+                            tv[u][c][3] = ok ? x.w : 0u;
+                        } else {
+#pragma unroll
+                            for (int e = 0; e < 4; e++) {
+                                const uint32_t cc = col + e;
+                                const uint32_t x = trow[cc < dim ? cc : dim - 1];
+                                tv[u][c][e] = (ok && cc < dim) ? x : 0u;
+                            }
+                        }
+                    }
+                    yv[u] = shw[rs * SHP + k];
+                }
+#pragma unroll
+                for (int u = 0; u < (int)U; u++)
+#pragma unroll
+                    for (int c = 0; c < KCH; c++)
+#pragma unroll
+                        for (int e = 0; e < 4; e++)
+                            accw[0][c][e] += yv[u] * tv[u][c][e];
+            }
+            continue;
         }
         __syncthreads(); // the previous step's readers are done with sh (and the roots were read)
         if (ln < S_used) {
