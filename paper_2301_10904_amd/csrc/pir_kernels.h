@@ -21,9 +21,11 @@
 //   * Each lane then walks its own subtree of height h depth-first with the
 //     path (both children of every node on it) in registers: every node is
 //     evaluated once and no seed below the lane's root ever leaves the VGPRs.
-//   * Each step of that walk yields two leaf shares per lane; they go to LDS
-//     and the workgroup immediately multiplies them into the streamed table
-//     rows (coalesced: one wave reads one 256-byte row per instruction).
+//   * Each step of that walk yields two leaf shares per lane.  A wave holds
+//     all Q keys over its own subtrees, so it passes the shares through a
+//     private LDS slot and immediately multiplies them into the table rows
+//     of those subtrees (coalesced 256-byte rows); no workgroup barrier is
+//     needed in the walk.
 //   * Partial sums are reduced across waves in LDS and added with 32-bit
 //     atomics into out; integer addition mod 2^32 makes the result exact and
 //     independent of the order.
@@ -123,8 +125,7 @@ struct Smem {
     static constexpr uint32_t W = TABW > QMAX * PIR_MAX_DIM ? TABW : QMAX * PIR_MAX_DIM;
     uint32_t tab[W];
     union {
-        Seed bfs[NT];              // breadth-first nodes
-        uint32_t sh[2 * NT];       // leaf shares of one walk step: [2 S][Q]
+        Seed bfs[NT];              // breadth-first nodes, then the waves' share slots
     } u;
     uint32_t keyok[QMAX];          // 0 = skip, 1 = party 0, 2 = party 1
 };
@@ -211,7 +212,6 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
                                                   uint64_t rows, uint32_t dim, uint32_t *__restrict__ out,
                                                   Geometry g)
 {
-    constexpr int S = NT / Q;
     __shared__ Smem<PRF::TAB_WORDS> sm;
 
     const uint32_t tid = threadIdx.x;
@@ -315,8 +315,12 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         __syncthreads();
     }
 
-    // per-lane depth-first walk of a subtree of height h
-    const uint32_t q = tid / S, ln = tid % S;
+    // per-lane depth-first walk of a subtree of height h.  Lane l of wave w
+    // evaluates key q = l mod Q over subtree position w P + l / Q (P = 64 / Q
+    // positions per wave), so each wave holds every key of the item over its
+    // own P subtrees.
+    constexpr uint32_t P_W = 64 / Q;
+    const uint32_t q = lane % Q, lnw = lane / Q, ln = wave * P_W + lnw;
     const uint32_t S_used = 1u << g.lgS;
     const bool active = ln < S_used && sm.keyok[q];
     const uint32_t h = g.H - g.lgS;       // >= 1
@@ -348,24 +352,19 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             for (int e = 0; e < 4; e++)
                 accw[i][c][e] = 0;
 
-    // Several keys share every row of the chunk, so the workgroup gathers the
-    // shares of all keys for a row before the row is read (two barriers per
-    // step).  With one key every row belongs to exactly one lane's subtree:
-    // each wave then multiplies the rows of its own lanes' leaves and needs
-    // no other wave, so the waves drift apart and the tree work of some
-    // overlaps the table stream of others.  In that case lane (rs, cg) =
-    // (lane / 16, lane mod 16) reads 16-byte column group cg of wave-row
-    // r = 4 k + rs, k = 0..31, which is leaf r mod 2 of the step in the
-    // subtree of lane r / 2; the shares go through a wave-private LDS slot as
-    // shw[r mod 4][r / 4], rows padded to 36 words so that the four row slots
-    // fall in different banks.
-    uint32_t(*sh)[Q] = reinterpret_cast<uint32_t(*)[Q]>(sm.u.sh);
-    constexpr uint32_t SHP = 36;
+    // Every row of the chunk lies in exactly one subtree position, and the
+    // wave owning that position holds the shares of all Q keys for it: each
+    // wave multiplies the R = 2 P rows of its step into its accumulators
+    // (every row is read once per item) and needs no other wave.  With no
+    // workgroup barrier in the walk the waves drift apart, and the tree work
+    // of some overlaps the table loads of others.  Wave-row r is leaf r mod 2
+    // of the step at position r / 2; its share for key q goes through a
+    // wave-private LDS slot at (r mod 4) SHP + (r / 4) Q + q, rows padded to
+    // SHP = 36 words so that the four row slots fall in different banks.
+    constexpr uint32_t R_W = 2 * P_W, SHP = 36;
     uint32_t *shw = reinterpret_cast<uint32_t *>(sm.u.bfs) + wave * 4 * SHP;
-    const uint32_t lane0 = wave * 64;
-    if (Q == 1)
-        __syncthreads(); // every lane has read its node: the breadth-first area is free
-    const uint32_t n_steps = (Q == 1 && lane0 >= S_used) ? 0u : steps; // a wave with no lane in use
+    __syncthreads(); // every lane has read its node: the breadth-first area is free
+    const uint32_t n_steps = wave * P_W >= S_used ? 0u : steps; // a wave with no position in use
     for (uint32_t m = 0; m < n_steps; m++) {
         uint32_t kst;
         if (m == 0) {
@@ -395,23 +394,26 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             y0 ^= cw.x;
             y1 ^= cw.y;
         }
-        if constexpr (Q == 1) {
-            // the previous step's reads of the slot come first in this wave's LDS order
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            shw[(2 * (lane & 1)) * SHP + (lane >> 1)] = y0;
-            shw[(2 * (lane & 1) + 1) * SHP + (lane >> 1)] = y1;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            constexpr uint32_t U = KCH >= 4 ? 2 : 8 / KCH;
+        // the previous step's reads of the slot come first in this wave's LDS order
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        shw[(2 * (lnw & 1)) * SHP + (lnw >> 1) * Q + q] = y0;
+        shw[(2 * (lnw & 1) + 1) * SHP + (lnw >> 1) * Q + q] = y1;
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        if constexpr (WIDE) {
+            // lane = (row slot rs = lane / 16, column group cg = lane mod 16):
+            // one 16-byte load covers 4 columns of row 4 k + rs, and U rows of
+            // a slot are in flight before any is used
+            constexpr uint32_t U = 8 / (Q * KCH);
             const uint32_t rs = lane >> 4, cg = lane & 15;
 #pragma unroll 1 // one group of U rows in flight per wave; more costs occupancy
-            for (uint32_t k0 = 0; k0 < 32; k0 += U) {
-                uint32_t tv[U][KCH][4], yv[U];
+            for (uint32_t k0 = 0; k0 < R_W / 4; k0 += U) {
+                uint32_t tv[U][KCH][4], yv[U][Q];
 #pragma unroll
                 for (int u = 0; u < (int)U; u++) {
-                    const uint32_t k = k0 + u, j = lane0 + 2 * k + (rs >> 1);
+                    const uint32_t k = k0 + u, j = wave * P_W + 2 * k + (rs >> 1);
                     const uint64_t row = row_base + ((uint64_t)j << h) + 2 * m + (rs & 1);
                     const bool ok = j < S_used && row < rows;
                     const uint32_t *trow = table + (ok ? row : 0) * dim;
@@ -434,84 +436,32 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
                             }
                         }
                     }
-                    yv[u] = shw[rs * SHP + k];
+#pragma unroll
+                    for (int qq = 0; qq < Q; qq++)
+                        yv[u][qq] = shw[rs * SHP + k * Q + qq];
                 }
 #pragma unroll
                 for (int u = 0; u < (int)U; u++)
 #pragma unroll
-                    for (int c = 0; c < KCH; c++)
-#pragma unroll
-                        for (int e = 0; e < 4; e++)
-                            accw[0][c][e] += yv[u] * tv[u][c][e];
-            }
-            continue;
-        }
-        __syncthreads(); // the previous step's readers are done with sh (and the roots were read)
-        if (ln < S_used) {
-            sh[2 * ln][q] = y0;
-            sh[2 * ln + 1][q] = y1;
-        }
-        __syncthreads();
-        const uint32_t n_rows = 2 * S_used;
-        if (WIDE) {
-            // lane = (row slot rs = lane / 16, column group cg = lane mod 16):
-            // one 16-byte load covers 4 columns, a wave covers 4 rows per
-            // load, and U loads are in flight before any is used
-            constexpr int U = KCH >= 4 ? 1 : 4 / KCH;
-            const uint32_t rs = lane >> 4, cg = lane & 15;
-            for (uint32_t i0 = wave * 4; i0 < n_rows; i0 += NW * 4 * U) {
-                uint32_t tv[U][KCH][4];
-#pragma unroll
-                for (int u = 0; u < U; u++) {
-                    const uint32_t i = i0 + u * NW * 4 + rs;
-                    const uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
-                    const bool ok = i < n_rows && row < rows;
-                    const uint32_t *trow = table + (ok ? row : 0) * dim;
-#pragma unroll
-                    for (int c = 0; c < KCH; c++) {
-                        const uint32_t col = 64 * c + 4 * cg;
-                        if (VEC4) {
-                            const uint4 x = col < dim ? *reinterpret_cast<const uint4 *>(trow + col) : make_uint4(0, 0, 0, 0);
-                            tv[u][c][0] = ok ? x.x : 0u;
-                            tv[u][c][1] = ok ? x.y : 0u;
-                            tv[u][c][2] = ok ? x.z : 0u;
-                            tv[u][c][3] = ok ? x.w : 0u;
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < 4; e++) {
-                                const uint32_t cc = col + e;
-                                const uint32_t x = trow[cc < dim ? cc : dim - 1];
-                                tv[u][c][e] = (ok && cc < dim) ? x : 0u;
-                            }
-                        }
-                    }
-                }
-#pragma unroll
-                for (int u = 0; u < U; u++) {
-                    const uint32_t i = i0 + u * NW * 4 + rs;
-                    const uint32_t ii = i < n_rows ? i : 0; // masked rows add zero
-#pragma unroll
-                    for (int qq = 0; qq < Q; qq++) {
-                        const uint32_t y = sh[ii][qq];
+                    for (int qq = 0; qq < Q; qq++)
 #pragma unroll
                         for (int c = 0; c < KCH; c++)
 #pragma unroll
                             for (int e = 0; e < 4; e++)
-                                accw[qq][c][e] += y * tv[u][c][e];
-                    }
-                }
+                                accw[qq][c][e] += yv[u][qq] * tv[u][c][e];
             }
         } else {
             // lane = column: U rows per round, their words loaded together
             // (clamped addresses, masked values) so the loads overlap
-            constexpr int U = (Q * KCH >= 32) ? 2 : (Q * KCH >= 8 ? 4 : 8);
-            for (uint32_t i0 = wave; i0 < n_rows; i0 += NW * U) {
+            constexpr uint32_t U = (Q * KCH >= 32) ? 2 : (Q * KCH >= 8 ? 4 : 8);
+#pragma unroll 1
+            for (uint32_t r0 = 0; r0 < R_W; r0 += U) {
                 uint32_t tv[U][KCH];
 #pragma unroll
-                for (int u = 0; u < U; u++) {
-                    const uint32_t i = i0 + u * NW;
-                    const uint64_t row = row_base + ((uint64_t)(i >> 1) << h) + 2 * m + (i & 1);
-                    const bool ok = i < n_rows && row < rows;
+                for (int u = 0; u < (int)U; u++) {
+                    const uint32_t r = r0 + u, j = wave * P_W + (r >> 1);
+                    const uint64_t row = row_base + ((uint64_t)j << h) + 2 * m + (r & 1);
+                    const bool ok = j < S_used && row < rows;
                     const uint32_t *trow = table + (ok ? row : 0) * dim;
 #pragma unroll
                     for (int c = 0; c < KCH; c++) {
@@ -521,12 +471,11 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
                     }
                 }
 #pragma unroll
-                for (int u = 0; u < U; u++) {
-                    const uint32_t i = i0 + u * NW;
-                    const uint32_t ii = i < n_rows ? i : 0;
+                for (int u = 0; u < (int)U; u++) {
+                    const uint32_t r = r0 + u;
 #pragma unroll
                     for (int qq = 0; qq < Q; qq++) {
-                        const uint32_t y = sh[ii][qq];
+                        const uint32_t y = shw[(r & 3) * SHP + (r >> 2) * Q + qq];
 #pragma unroll
                         for (int c = 0; c < KCH; c++)
                             acc[qq][c] += y * tv[u][c];

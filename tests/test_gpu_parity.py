@@ -369,3 +369,28 @@ def test_max_domain_2p32_rows(O, pirmod, nkeys):
         assert (r == dense.get(int(alphas[p]), np.zeros(dim, np.uint32))).all(), p
     del Ts
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+def test_small_groups_every_shape(O, pirmod, prf):
+    """1..16 keys (every key-group size of the small-batch kernel, and the
+    wave kernel above its threshold) on tiny to mid-size domains, where some
+    waves of a workgroup hold no subtree, with row widths of every column
+    class (1, 7, 64, 65, 200 words): every per-server answer bit-exact."""
+    import torch
+
+    for rows in (1, 2, 7, 64, 300, 5000):
+        n = log_domain(rows)
+        for dim in (1, 7, 64, 65, 200):
+            T = W.make_table(rows, dim, rows + dim)
+            Tn = T.numpy().view(np.uint32)
+            Td = T.cuda()
+            for nk in (1, 2, 3, 5, 8, 16):
+                seed = 7 * rows + dim + nk
+                alphas = W.uniform_indices(rows, nk, seed)
+                K, _ = O.gen_batch(n, alphas, W.key_seeds(nk, seed), prf_id=prf)
+                out = pirmod.answer(torch.from_numpy(K).cuda(), Td, prf=prf)
+                torch.cuda.synchronize()
+                got = out.cpu().numpy().view(np.uint32)
+                want = O.answer_batch(K, Tn, nthreads=cpu_threads())
+                assert (got == want).all(), (rows, dim, nk)
