@@ -165,15 +165,24 @@ static int wave_class(uint32_t dim)
 }
 
 // Which kernel answers one table: the wave kernel (int8 matrix cores, up to 16
-// keys per wave) from a PRF-dependent batch size on, else the small-batch
-// kernel, which also takes rows wider than 64 words.  A wave item costs the
-// same for 9..16 keys; measured on 2^20 x 64 rows it beats the small-batch
-// kernel from 9 keys with AES-128 (0.62 against 0.69 ms at 15 keys) but only
-// from 17 with ChaCha20 (0.59 against 0.66 ms at 16 keys).
-static uint32_t wave_min_keys(uint32_t prf_id) { return prf_id == PIR_PRF_CHACHA20 ? 17u : 9u; }
+// keys per wave) from a batch size on that depends on the PRF and the domain,
+// else the small-batch kernel, which also takes rows wider than 64 words.  A
+// wave item costs the same for 9..16 keys.  Every lane of the wave kernel
+// walks its own path from the root, while the small-batch kernel shares the
+// path above its chunks; for small domains that repeated descent outweighs
+// the matrix-core contraction.  Measured at 9..16 keys: on 2^20 x 64 rows the
+// small-batch kernel takes 0.49 ms against 0.59 (AES-128), on 2^22 rows 1.90
+// against 1.60 ms; with ChaCha20 the wave kernel wins from 17 keys at both
+// sizes (1.05 against 1.12 ms at 2^20), and with either PRF from 24 keys.
+static uint32_t wave_min_keys(uint32_t prf_id, uint32_t n)
+{
+    if (prf_id == PIR_PRF_CHACHA20)
+        return 17u;
+    return n <= 20 ? 17u : 9u;
+}
 static bool use_wave_kernel(uint32_t prf_id, uint32_t n_keys, uint32_t n, uint32_t dim)
 {
-    return n_keys >= wave_min_keys(prf_id) && n >= 3 && dim <= 64;
+    return n_keys >= wave_min_keys(prf_id, n) && n >= 3 && dim <= 64;
 }
 
 // Work plan of the small-batch kernel: Q keys per workgroup, chunks of 2^H

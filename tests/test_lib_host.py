@@ -226,23 +226,27 @@ def test_plan_small_wave_batches_fill_the_gpu():
     """Few key groups: the subtree height drops below the register limit (9)
     until the items fill the GPU's 4096 wave slots, but not so far that the
     per-lane descent dominates; many groups keep the full height."""
-    p = pir.plan(16, 1 << 20, 64)
+    p = pir.plan(16, 1 << 21, 64)  # one key group
     assert p["kernel"] == pir.KERNEL_WAVES
-    assert p["items"] == 4096 and p["subtree_log"] == 6
-    assert p["descent_levels"] + p["subtree_log"] == 20
+    assert p["items"] == 4096 and p["subtree_log"] == 7
+    assert p["descent_levels"] + p["subtree_log"] == 21
+    p = pir.plan(32, 1 << 20, 64)  # two key groups
+    assert p["items"] == 4096 and p["subtree_log"] == 7
     assert pir.plan(64, 1 << 20, 64)["subtree_log"] == 7
     assert pir.plan(128, 1 << 20, 64)["subtree_log"] == 8
     for keys in (256, 1024, 4096):
         assert pir.plan(keys, 1 << 20, 64)["subtree_log"] == 9
-    for keys in (16, 17, 31, 40, 100, 300, 5000):
+    for keys in (17, 31, 40, 100, 300, 5000):
         p = pir.plan(keys, 1 << 20, 64)
         assert p["items"] >= 4096 and 3 <= p["subtree_log"] <= 9, (keys, p)
 
 
 def test_plan_kernel_choice():
     assert pir.plan(1024, 1 << 20, 65)["kernel"] == pir.KERNEL_SMALL_BATCH   # rows wider than 64 words
-    assert pir.plan(8, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH      # up to 8 keys (AES-128)
-    assert pir.plan(9, 1 << 20, 64)["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(16, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH     # AES-128, up to 2^20 rows: 16 keys
+    assert pir.plan(17, 1 << 20, 64)["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(8, (1 << 20) + 1, 64)["kernel"] == pir.KERNEL_SMALL_BATCH  # larger domains: 8 keys
+    assert pir.plan(9, (1 << 20) + 1, 64)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(16, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH  # ChaCha20: 16
     assert pir.plan(17, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(64, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH            # n = 2: too small for waves
@@ -256,7 +260,7 @@ def test_plan_kernel_choice():
         n = max(1, (rows - 1).bit_length())
         assert p["n"] == n
         if p["kernel"] == pir.KERNEL_WAVES:
-            assert keys >= 9 and dim <= 64 and n >= 3
+            assert keys >= (17 if n <= 20 else 9) and dim <= 64 and n >= 3
             assert p["descent_levels"] + p["subtree_log"] == n
             chunks = -(-rows // p["rows_per_item"])
             assert p["items"] == chunks * -(-keys // 16)
