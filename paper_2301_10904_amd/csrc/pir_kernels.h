@@ -565,14 +565,15 @@ __device__ __forceinline__ uint32_t arrange(uint32_t x)
 
 __device__ __forceinline__ long pack2(uint32_t lo, uint32_t hi) { return (long)(((uint64_t)hi << 32) | lo); }
 
-// KT consecutive words T[r][c0 .. c0 + KT - 1] (zero outside the table).
-// VEC: dim == 16 KT, so the words are in bounds and 4 KT-byte aligned.
+// KT consecutive words T[r][c0 .. c0 + KT - 1]; a row past the table reads the
+// last row instead (its share is zeroed by the caller), and columns past dim
+// read zero (VEC: dim == 16 KT, so the words are in bounds and 4 KT-byte
+// aligned).
 template <int KT, bool VEC>
 __device__ __forceinline__ void load_cols(const uint32_t *__restrict__ table, uint64_t r, uint64_t rows, uint32_t dim,
                                           uint32_t c0, uint32_t (&v)[KT])
 {
-    const bool row_ok = r < rows;
-    const uint32_t *p = table + (row_ok ? r : rows - 1) * dim;
+    const uint32_t *p = table + (r < rows ? r : rows - 1) * dim;
     if (VEC) {
         if (KT == 4) {
             const uint4 x = *reinterpret_cast<const uint4 *>(p + c0);
@@ -587,15 +588,12 @@ __device__ __forceinline__ void load_cols(const uint32_t *__restrict__ table, ui
         } else {
             v[0] = p[c0];
         }
-#pragma unroll
-        for (int t = 0; t < KT; t++)
-            v[t] = row_ok ? v[t] : 0u;
     } else {
 #pragma unroll
         for (int t = 0; t < KT; t++) {
             const uint32_t c = c0 + t;
             const uint32_t x = p[c < dim ? c : dim - 1];
-            v[t] = (row_ok && c < dim) ? x : 0u;
+            v[t] = c < dim ? x : 0u;
         }
     }
 }
@@ -698,7 +696,8 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
 
         uint32_t kst = 1; // step 0 starts at the lane's root, already in `node`
         if (m != 0) {
-            const uint32_t kf = h - 1 - __builtin_ctz(m);
+            // uniform over the wave: scalar compares select the path entry
+            const uint32_t kf = __builtin_amdgcn_readfirstlane(h - 1 - __builtin_ctz(m));
 #pragma unroll
             for (int i = 1; i < HMAX3; i++)
                 if ((uint32_t)i == kf)
@@ -707,7 +706,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
         }
         uint32_t y0 = 0, y1 = 0;
         if (active) {
-            for (uint32_t k = kst; k < h; k++) {
+            for (uint32_t k = __builtin_amdgcn_readfirstlane(kst); k < h; k++) {
                 Seed c0, c1;
                 children(P, K, node, d0 + k, c0, c1);
 #pragma unroll
@@ -718,8 +717,8 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
             }
             const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
             P.pair_word0(node.w, y0, y1);
-            y0 ^= cw.x;
-            y1 ^= cw.y;
+            y0 = r0 < rows ? y0 ^ cw.x : 0u; // rows past the table add nothing
+            y1 = r0 + 1 < rows ? y1 ^ cw.y : 0u;
         }
 
         const uint32_t e0 = balanced(y0), e1 = balanced(y1);
