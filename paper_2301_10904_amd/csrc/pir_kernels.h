@@ -565,15 +565,13 @@ __device__ __forceinline__ uint32_t arrange(uint32_t x)
 
 __device__ __forceinline__ long pack2(uint32_t lo, uint32_t hi) { return (long)(((uint64_t)hi << 32) | lo); }
 
-// KT consecutive words T[r][c0 .. c0 + KT - 1]; a row past the table reads the
-// last row instead (its share is zeroed by the caller), and columns past dim
+// KT consecutive words p[c0 .. c0 + KT - 1] of the row at p; columns past dim
 // read zero (VEC: dim == 16 KT, so the words are in bounds and 4 KT-byte
 // aligned).
 template <int KT, bool VEC>
-__device__ __forceinline__ void load_cols(const uint32_t *__restrict__ table, uint64_t r, uint64_t rows, uint32_t dim,
-                                          uint32_t c0, uint32_t (&v)[KT])
+__device__ __forceinline__ void load_cols(const uint32_t *__restrict__ p, uint32_t dim, uint32_t c0,
+                                          uint32_t (&v)[KT])
 {
-    const uint32_t *p = table + (r < rows ? r : rows - 1) * dim;
     if (VEC) {
         if (KT == 4) {
             const uint4 x = *reinterpret_cast<const uint4 *>(p + c0);
@@ -628,7 +626,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
         __syncthreads();
     }
 
-    const uint32_t item0 = xcd_block() * NW3 + wave;
+    const uint32_t item0 = __builtin_amdgcn_readfirstlane(xcd_block() * NW3 + wave); // uniform over the wave
     if (item0 >= tasks.n_items)
         return; // whole wave; no barrier follows
     uint32_t ti = 0; // the table this item belongs to (tasks are in item order)
@@ -685,14 +683,22 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
     // this lane's table columns: tile t, column n = lane mod 16 -> n * KT + t
     const uint32_t col0 = (lane & 15) * KT;
     const uint32_t steps = 1u << (h - 1);
-    for (uint32_t m = 0; m < steps; m++) {
+    // The item's rows: a chunk of at most 4 2^h <= 2048 rows from chunk_row0,
+    // read through 32-bit word offsets from the chunk's first row; a row past
+    // the table reads the chunk's last row instead (its share is zero).
+    const uint64_t chunk_row0 = ((uint64_t)chunk * 4) << h;
+    const uint32_t *__restrict__ ctab = table + chunk_row0 * dim;
+    const uint64_t chunk_rows = rows - chunk_row0 < ((uint64_t)4 << h) ? rows - chunk_row0 : ((uint64_t)4 << h);
+    const uint32_t last_off = (uint32_t)(chunk_rows - 1) * dim;
+    uint32_t row_off = (sub << h) * dim; // this lane's row 2m
+    for (uint32_t m = 0; m < steps; m++, row_off += 2 * dim) {
         // table words of the two rows this lane feeds to the product; issued
-        // first and unconditionally (clamped addresses, masked values), so
-        // their latency hides behind this step's AES work
+        // first and unconditionally (clamped rows), so their latency hides
+        // behind this step's AES work
         const uint64_t r0 = lane_row0 + 2 * m;
         uint32_t t0[KT], t1[KT];
-        load_cols<KT, VEC>(table, r0, rows, dim, col0, t0);
-        load_cols<KT, VEC>(table, r0 + 1, rows, dim, col0, t1);
+        load_cols<KT, VEC>(ctab + (row_off < last_off ? row_off : last_off), dim, col0, t0);
+        load_cols<KT, VEC>(ctab + (row_off + dim < last_off ? row_off + dim : last_off), dim, col0, t1);
 
         uint32_t kst = 1; // step 0 starts at the lane's root, already in `node`
         if (m != 0) {
