@@ -204,6 +204,102 @@ struct Geometry {
     uint32_t n_chunks; // row chunks
 };
 
+// ---------------------------------------------------------------------------
+// The share x table product on the int8 matrix cores (v_mfma_i32_16x16x32_i8:
+// A lane l holds row l mod 16, K slice (l / 16) * 8 .. +7).
+//
+// Exactness mod 2^32 on int8 units: a uint32 x has balanced base-256 digits
+// d_0..d_3 in [-128, 127] with x = sum d_a 256^a (mod 2^32); they are the bytes
+// of (x + 0x80808080) ^ 0x80808080.  Then
+//     y * T = sum_{s=0..3} 256^s * sum_{a+b=s} d_a(y) e_b(T)      (mod 2^32),
+// so for each s one MFMA with A = digits of y arranged d_s, d_{s-1}, .., d_0
+// and B = digits of T gives the s-th term; the int32 accumulators wrap mod 2^32.
+// Each step folds its four terms into one running sum per tile.
+// ---------------------------------------------------------------------------
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint32_t balanced(uint32_t x) { return (x + 0x80808080u) ^ 0x80808080u; }
+
+// digits of x arranged for shift s: byte j holds d_{s-j} (0 where j > s)
+template <int S>
+__device__ __forceinline__ uint32_t arrange(uint32_t x)
+{
+    if (S == 0)
+        return x & 0xffu;
+    constexpr uint32_t sel = S == 1 ? 0x0c0c0001u : S == 2 ? 0x0c000102u : 0x00010203u;
+    return __builtin_amdgcn_perm(x, x, sel);
+}
+
+__device__ __forceinline__ long pack2(uint32_t lo, uint32_t hi) { return (long)(((uint64_t)hi << 32) | lo); }
+
+// KT consecutive words p[c0 .. c0 + KT - 1] of the row at p; columns past dim
+// read zero (VEC: dim == 16 KT, so the words are in bounds and 4 KT-byte
+// aligned).
+template <int KT, bool VEC>
+__device__ __forceinline__ void load_cols(const uint32_t *__restrict__ p, uint32_t dim, uint32_t c0,
+                                          uint32_t (&v)[KT])
+{
+    if (VEC) {
+        if (KT == 4) {
+            const uint4 x = *reinterpret_cast<const uint4 *>(p + c0);
+            v[0] = x.x;
+            v[KT > 1 ? 1 : 0] = x.y;
+            v[KT > 2 ? 2 : 0] = x.z;
+            v[KT > 3 ? 3 : 0] = x.w;
+        } else if (KT == 2) {
+            const uint2 x = *reinterpret_cast<const uint2 *>(p + c0);
+            v[0] = x.x;
+            v[KT > 1 ? 1 : 0] = x.y;
+        } else {
+            v[0] = p[c0];
+        }
+    } else {
+#pragma unroll
+        for (int t = 0; t < KT; t++) {
+            const uint32_t c = c0 + t;
+            const uint32_t x = p[c < dim ? c : dim - 1];
+            v[t] = c < dim ? x : 0u;
+        }
+    }
+}
+
+// One walk step's product on the matrix cores: the 64 lanes hold the shares
+// y0, y1 of rows 2m, 2m+1 of their subtrees (lane l: key l mod 16, subtree
+// l / 16) and the table words t0, t1 of those rows at columns
+// (l mod 16) KT + t; tot[t] accumulates the [16 keys x 16 columns] tile t.
+template <int KT>
+__device__ __forceinline__ void mfma_step(uint32_t y0, uint32_t y1, const uint32_t (&t0)[KT],
+                                          const uint32_t (&t1)[KT], v4i (&tot)[KT])
+{
+    const uint32_t e0 = balanced(y0), e1 = balanced(y1);
+    const long a0 = pack2(arrange<0>(e0), arrange<0>(e1));
+    const long a1 = pack2(arrange<1>(e0), arrange<1>(e1));
+    const long a2 = pack2(arrange<2>(e0), arrange<2>(e1));
+    const long a3 = pack2(arrange<3>(e0), arrange<3>(e1));
+    const v4i zero = {0, 0, 0, 0};
+#pragma unroll
+    for (int t = 0; t < KT; t++) {
+        // tot += D_0 + 2^8 (D_1 + 2^8 (D_2 + 2^8 D_3)): D_0 accumulates in
+        // the matrix core, the rest is three shift-and-add steps per word
+        const long b = pack2(balanced(t0[t]), balanced(t1[t]));
+        const v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b, zero, 0, 0, 0);
+        const v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a2, b, zero, 0, 0, 0);
+        const v4i c3 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3, b, zero, 0, 0, 0);
+        v4i acc = tot[t];
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            // the empty asm keeps each (x << 8) + y a single v_lshl_add_u32
+            // (the compiler would otherwise expand the chain into separate shifts)
+            uint32_t hi = ((uint32_t)c3[i] << 8) + (uint32_t)c2[i];
+            asm volatile("" : "+v"(hi));
+            hi = (hi << 8) + (uint32_t)c1[i];
+            asm volatile("" : "+v"(hi));
+            acc[i] = (int)((uint32_t)acc[i] + (hi << 8));
+        }
+        tot[t] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b, acc, 0, 0, 0);
+    }
+}
+
 // Q keys per group (Q <= QMAX); KCH column chunks of 64 (dim <= 64 KCH);
 // VEC4: dim is a multiple of 4 (16-byte row segments are aligned).
 template <class PRF, int Q, int KCH, bool VEC4>
@@ -335,14 +431,22 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         right[i] = Seed{{0, 0, 0, 0}};
 
     // WIDE: few accumulators per column; a lane then owns 4 columns of one of
-    // 4 row slots, otherwise one column of every row
+    // 4 row slots, otherwise one column of every row.  MF: sixteen keys and
+    // rows of at most 64 words; the lanes are then laid out as the matrix
+    // cores' operands (key lane mod 16, subtree position lane / 16) and the
+    // product runs on them (mfma_step), four tiles of 16 columns.
     constexpr bool WIDE = Q * KCH <= 4;
-    uint32_t acc[WIDE ? 1 : Q][WIDE ? 1 : KCH];
+    constexpr bool MF = Q == 16 && KCH == 1;
+    uint32_t acc[WIDE || MF ? 1 : Q][WIDE || MF ? 1 : KCH];
     uint32_t accw[WIDE ? Q : 1][WIDE ? KCH : 1][4];
+    v4i tot[MF ? 4 : 1];
 #pragma unroll
-    for (int i = 0; i < (WIDE ? 1 : Q); i++)
+    for (int t = 0; t < (MF ? 4 : 1); t++)
+        tot[t] = v4i{0, 0, 0, 0};
 #pragma unroll
-        for (int c = 0; c < (WIDE ? 1 : KCH); c++)
+    for (int i = 0; i < (WIDE || MF ? 1 : Q); i++)
+#pragma unroll
+        for (int c = 0; c < (WIDE || MF ? 1 : KCH); c++)
             acc[i][c] = 0;
 #pragma unroll
     for (int i = 0; i < (WIDE ? Q : 1); i++)
@@ -366,6 +470,23 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     __syncthreads(); // every lane has read its node: the breadth-first area is free
     const uint32_t n_steps = wave * P_W >= S_used ? 0u : steps; // a wave with no position in use
     for (uint32_t m = 0; m < n_steps; m++) {
+        // MF: this lane's two rows (leaves 2m, 2m+1 of its subtree), loaded
+        // before the step's tree work so that their latency hides behind it; a
+        // row past the table reads the last row and gets a zero share
+        uint32_t t0[MF ? 4 : 1], t1[MF ? 4 : 1];
+        const uint64_t mrow = MF ? row_base + ((uint64_t)ln << h) + 2 * m : 0;
+        if constexpr (MF) {
+            const uint32_t *p0 = table + (mrow < rows ? mrow : rows - 1) * dim;
+            const uint32_t *p1 = table + (mrow + 1 < rows ? mrow + 1 : rows - 1) * dim;
+            const uint32_t c0 = (lane & 15) * 4;
+            if (dim == 64) {
+                load_cols<4, true>(p0, dim, c0, t0);
+                load_cols<4, true>(p1, dim, c0, t1);
+            } else {
+                load_cols<4, false>(p0, dim, c0, t0);
+                load_cols<4, false>(p1, dim, c0, t1);
+            }
+        }
         uint32_t kst;
         if (m == 0) {
             node = root;
@@ -394,91 +515,95 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             y0 ^= cw.x;
             y1 ^= cw.y;
         }
-        // the previous step's reads of the slot come first in this wave's LDS order
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        shw[(2 * (lnw & 1)) * SHP + (lnw >> 1) * Q + q] = y0;
-        shw[(2 * (lnw & 1) + 1) * SHP + (lnw >> 1) * Q + q] = y1;
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        if constexpr (WIDE) {
-            // lane = (row slot rs = lane / 16, column group cg = lane mod 16):
-            // one 16-byte load covers 4 columns of row 4 k + rs, and U rows of
-            // a slot are in flight before any is used
-            constexpr uint32_t U = 8 / (Q * KCH);
-            const uint32_t rs = lane >> 4, cg = lane & 15;
-#pragma unroll 1 // one group of U rows in flight per wave; more costs occupancy
-            for (uint32_t k0 = 0; k0 < R_W / 4; k0 += U) {
-                uint32_t tv[U][KCH][4], yv[U][Q];
-#pragma unroll
-                for (int u = 0; u < (int)U; u++) {
-                    const uint32_t k = k0 + u, j = wave * P_W + 2 * k + (rs >> 1);
-                    const uint64_t row = row_base + ((uint64_t)j << h) + 2 * m + (rs & 1);
-                    const bool ok = j < S_used && row < rows;
-                    const uint32_t *trow = table + (ok ? row : 0) * dim;
-#pragma unroll
-                    for (int c = 0; c < KCH; c++) {
-                        const uint32_t col = 64 * c + 4 * cg;
-                        if (VEC4) {
-                            const uint4 x =
-                                col < dim ? *reinterpret_cast<const uint4 *>(trow + col) : make_uint4(0, 0, 0, 0);
-                            tv[u][c][0] = ok ? x.x : 0u;
-                            tv[u][c][1] = ok ? x.y : 0u;
-                            tv[u][c][2] = ok ? x.z : 0u;
-                            tv[u][c][3] = ok ? x.w : 0u;
-                        } else {
-#pragma unroll
-                            for (int e = 0; e < 4; e++) {
-                                const uint32_t cc = col + e;
-                                const uint32_t x = trow[cc < dim ? cc : dim - 1];
-                                tv[u][c][e] = (ok && cc < dim) ? x : 0u;
+        if constexpr (MF) {
+            mfma_step<4>(mrow < rows ? y0 : 0u, mrow + 1 < rows ? y1 : 0u, t0, t1, tot);
+        } else {
+            // the previous step's reads of the slot come first in this wave's LDS order
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            shw[(2 * (lnw & 1)) * SHP + (lnw >> 1) * Q + q] = y0;
+            shw[(2 * (lnw & 1) + 1) * SHP + (lnw >> 1) * Q + q] = y1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+            if constexpr (WIDE) {
+                // lane = (row slot rs = lane / 16, column group cg = lane mod 16):
+                // one 16-byte load covers 4 columns of row 4 k + rs, and U rows of
+                // a slot are in flight before any is used
+                constexpr uint32_t U = 8 / (Q * KCH);
+                const uint32_t rs = lane >> 4, cg = lane & 15;
+    #pragma unroll 1 // one group of U rows in flight per wave; more costs occupancy
+                for (uint32_t k0 = 0; k0 < R_W / 4; k0 += U) {
+                    uint32_t tv[U][KCH][4], yv[U][Q];
+    #pragma unroll
+                    for (int u = 0; u < (int)U; u++) {
+                        const uint32_t k = k0 + u, j = wave * P_W + 2 * k + (rs >> 1);
+                        const uint64_t row = row_base + ((uint64_t)j << h) + 2 * m + (rs & 1);
+                        const bool ok = j < S_used && row < rows;
+                        const uint32_t *trow = table + (ok ? row : 0) * dim;
+    #pragma unroll
+                        for (int c = 0; c < KCH; c++) {
+                            const uint32_t col = 64 * c + 4 * cg;
+                            if (VEC4) {
+                                const uint4 x =
+                                    col < dim ? *reinterpret_cast<const uint4 *>(trow + col) : make_uint4(0, 0, 0, 0);
+                                tv[u][c][0] = ok ? x.x : 0u;
+                                tv[u][c][1] = ok ? x.y : 0u;
+                                tv[u][c][2] = ok ? x.z : 0u;
+                                tv[u][c][3] = ok ? x.w : 0u;
+                            } else {
+    #pragma unroll
+                                for (int e = 0; e < 4; e++) {
+                                    const uint32_t cc = col + e;
+                                    const uint32_t x = trow[cc < dim ? cc : dim - 1];
+                                    tv[u][c][e] = (ok && cc < dim) ? x : 0u;
+                                }
                             }
                         }
+    #pragma unroll
+                        for (int qq = 0; qq < Q; qq++)
+                            yv[u][qq] = shw[rs * SHP + k * Q + qq];
                     }
-#pragma unroll
-                    for (int qq = 0; qq < Q; qq++)
-                        yv[u][qq] = shw[rs * SHP + k * Q + qq];
+    #pragma unroll
+                    for (int u = 0; u < (int)U; u++)
+    #pragma unroll
+                        for (int qq = 0; qq < Q; qq++)
+    #pragma unroll
+                            for (int c = 0; c < KCH; c++)
+    #pragma unroll
+                                for (int e = 0; e < 4; e++)
+                                    accw[qq][c][e] += yv[u][qq] * tv[u][c][e];
                 }
-#pragma unroll
-                for (int u = 0; u < (int)U; u++)
-#pragma unroll
-                    for (int qq = 0; qq < Q; qq++)
-#pragma unroll
-                        for (int c = 0; c < KCH; c++)
-#pragma unroll
-                            for (int e = 0; e < 4; e++)
-                                accw[qq][c][e] += yv[u][qq] * tv[u][c][e];
-            }
-        } else {
-            // lane = column: U rows per round, their words loaded together
-            // (clamped addresses, masked values) so the loads overlap
-            constexpr uint32_t U = (Q * KCH >= 32) ? 2 : (Q * KCH >= 8 ? 4 : 8);
-#pragma unroll 1
-            for (uint32_t r0 = 0; r0 < R_W; r0 += U) {
-                uint32_t tv[U][KCH];
-#pragma unroll
-                for (int u = 0; u < (int)U; u++) {
-                    const uint32_t r = r0 + u, j = wave * P_W + (r >> 1);
-                    const uint64_t row = row_base + ((uint64_t)j << h) + 2 * m + (r & 1);
-                    const bool ok = j < S_used && row < rows;
-                    const uint32_t *trow = table + (ok ? row : 0) * dim;
-#pragma unroll
-                    for (int c = 0; c < KCH; c++) {
-                        const uint32_t col = lane + 64 * c;
-                        const uint32_t x = trow[col < dim ? col : dim - 1];
-                        tv[u][c] = (ok && col < dim) ? x : 0u;
+            } else {
+                // lane = column: U rows per round, their words loaded together
+                // (clamped addresses, masked values) so the loads overlap
+                constexpr uint32_t U = (Q * KCH >= 32) ? 2 : (Q * KCH >= 8 ? 4 : 8);
+    #pragma unroll 1
+                for (uint32_t r0 = 0; r0 < R_W; r0 += U) {
+                    uint32_t tv[U][KCH];
+    #pragma unroll
+                    for (int u = 0; u < (int)U; u++) {
+                        const uint32_t r = r0 + u, j = wave * P_W + (r >> 1);
+                        const uint64_t row = row_base + ((uint64_t)j << h) + 2 * m + (r & 1);
+                        const bool ok = j < S_used && row < rows;
+                        const uint32_t *trow = table + (ok ? row : 0) * dim;
+    #pragma unroll
+                        for (int c = 0; c < KCH; c++) {
+                            const uint32_t col = lane + 64 * c;
+                            const uint32_t x = trow[col < dim ? col : dim - 1];
+                            tv[u][c] = (ok && col < dim) ? x : 0u;
+                        }
                     }
-                }
-#pragma unroll
-                for (int u = 0; u < (int)U; u++) {
-                    const uint32_t r = r0 + u;
-#pragma unroll
-                    for (int qq = 0; qq < Q; qq++) {
-                        const uint32_t y = shw[(r & 3) * SHP + (r >> 2) * Q + qq];
-#pragma unroll
-                        for (int c = 0; c < KCH; c++)
-                            acc[qq][c] += y * tv[u][c];
+    #pragma unroll
+                    for (int u = 0; u < (int)U; u++) {
+                        const uint32_t r = r0 + u;
+    #pragma unroll
+                        for (int qq = 0; qq < Q; qq++) {
+                            const uint32_t y = shw[(r & 3) * SHP + (r >> 2) * Q + qq];
+    #pragma unroll
+                            for (int c = 0; c < KCH; c++)
+                                acc[qq][c] += y * tv[u][c];
+                        }
                     }
                 }
             }
@@ -491,7 +616,17 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     for (uint32_t i = tid; i < Q * dim; i += NT)
         s_acc[i] = 0;
     __syncthreads();
-    if (WIDE) {
+    if constexpr (MF) {
+        // lane l holds D[(l / 16) 4 + i][(l mod 16) 4 + t] of tile t
+#pragma unroll
+        for (int t = 0; t < (MF ? 4 : 1); t++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const uint32_t col = (lane & 15) * 4 + t;
+                if (col < dim)
+                    atomicAdd(&s_acc[((lane >> 4) * 4 + i) * dim + col], (uint32_t)tot[t][i]);
+            }
+    } else if constexpr (WIDE) {
 #pragma unroll
         for (int qq = 0; qq < (WIDE ? Q : 1); qq++)
 #pragma unroll
@@ -535,66 +670,12 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
 // depth-first over the subtree with the path in registers.  Each walk step
 // gives a lane the shares of two consecutive rows, so the 64 lanes together
 // hold an [16 keys x 8 rows] share tile, exactly the A operand layout of
-// v_mfma_i32_16x16x32_i8 (lane l: row l mod 16, K slice (l / 16) * 8 .. +7).
-//
-// Exactness mod 2^32 on int8 units: a uint32 x has balanced base-256 digits
-// d_0..d_3 in [-128, 127] with x = sum d_a 256^a (mod 2^32); they are the bytes
-// of (x + 0x80808080) ^ 0x80808080.  Then
-//     y * T = sum_{s=0..3} 256^s * sum_{a+b=s} d_a(y) e_b(T)      (mod 2^32),
-// so for each s one MFMA with A = digits of y arranged d_s, d_{s-1}, .., d_0
-// and B = digits of T gives the s-th term; the int32 accumulators wrap mod 2^32.
-// Each step folds its four terms into one running sum per tile.
+// v_mfma_i32_16x16x32_i8 (lane l: row l mod 16, K slice (l / 16) * 8 .. +7),
+// and mfma_step() multiplies it into the table rows.
 // ---------------------------------------------------------------------------
-typedef int v4i __attribute__((ext_vector_type(4)));
-
 constexpr int NW3 = 8;             // waves per workgroup (two workgroups per CU)
 constexpr int HMAX3 = 9;           // largest per-lane subtree height of the wave kernel
 constexpr int NT3 = 64 * NW3;
-
-__device__ __forceinline__ uint32_t balanced(uint32_t x) { return (x + 0x80808080u) ^ 0x80808080u; }
-
-// digits of x arranged for shift s: byte j holds d_{s-j} (0 where j > s)
-template <int S>
-__device__ __forceinline__ uint32_t arrange(uint32_t x)
-{
-    if (S == 0)
-        return x & 0xffu;
-    constexpr uint32_t sel = S == 1 ? 0x0c0c0001u : S == 2 ? 0x0c000102u : 0x00010203u;
-    return __builtin_amdgcn_perm(x, x, sel);
-}
-
-__device__ __forceinline__ long pack2(uint32_t lo, uint32_t hi) { return (long)(((uint64_t)hi << 32) | lo); }
-
-// KT consecutive words p[c0 .. c0 + KT - 1] of the row at p; columns past dim
-// read zero (VEC: dim == 16 KT, so the words are in bounds and 4 KT-byte
-// aligned).
-template <int KT, bool VEC>
-__device__ __forceinline__ void load_cols(const uint32_t *__restrict__ p, uint32_t dim, uint32_t c0,
-                                          uint32_t (&v)[KT])
-{
-    if (VEC) {
-        if (KT == 4) {
-            const uint4 x = *reinterpret_cast<const uint4 *>(p + c0);
-            v[0] = x.x;
-            v[KT > 1 ? 1 : 0] = x.y;
-            v[KT > 2 ? 2 : 0] = x.z;
-            v[KT > 3 ? 3 : 0] = x.w;
-        } else if (KT == 2) {
-            const uint2 x = *reinterpret_cast<const uint2 *>(p + c0);
-            v[0] = x.x;
-            v[KT > 1 ? 1 : 0] = x.y;
-        } else {
-            v[0] = p[c0];
-        }
-    } else {
-#pragma unroll
-        for (int t = 0; t < KT; t++) {
-            const uint32_t c = c0 + t;
-            const uint32_t x = p[c < dim ? c : dim - 1];
-            v[t] = c < dim ? x : 0u;
-        }
-    }
-}
 
 // One table's share of a wave-kernel launch.  The table is cut into n_bins
 // bins of 2^n rows (the last may be shorter; one bin for a whole-table query)
@@ -727,33 +808,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
             y1 = r0 + 1 < rows ? y1 ^ cw.y : 0u;
         }
 
-        const uint32_t e0 = balanced(y0), e1 = balanced(y1);
-        const long a0 = pack2(arrange<0>(e0), arrange<0>(e1));
-        const long a1 = pack2(arrange<1>(e0), arrange<1>(e1));
-        const long a2 = pack2(arrange<2>(e0), arrange<2>(e1));
-        const long a3 = pack2(arrange<3>(e0), arrange<3>(e1));
-        const v4i zero = {0, 0, 0, 0};
-#pragma unroll
-        for (int t = 0; t < KT; t++) {
-            // tot += D_0 + 2^8 (D_1 + 2^8 (D_2 + 2^8 D_3)): D_0 accumulates in
-            // the matrix core, the rest is three shift-and-add steps per word
-            const long b = pack2(balanced(t0[t]), balanced(t1[t]));
-            const v4i c1 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a1, b, zero, 0, 0, 0);
-            const v4i c2 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a2, b, zero, 0, 0, 0);
-            const v4i c3 = __builtin_amdgcn_mfma_i32_16x16x32_i8(a3, b, zero, 0, 0, 0);
-            v4i acc = tot[t];
-#pragma unroll
-            for (int i = 0; i < 4; i++) {
-                // the empty asm keeps each (x << 8) + y a single v_lshl_add_u32
-                // (the compiler would otherwise expand the chain into separate shifts)
-                uint32_t hi = ((uint32_t)c3[i] << 8) + (uint32_t)c2[i];
-                asm volatile("" : "+v"(hi));
-                hi = (hi << 8) + (uint32_t)c1[i];
-                asm volatile("" : "+v"(hi));
-                acc[i] = (int)((uint32_t)acc[i] + (hi << 8));
-            }
-            tot[t] = __builtin_amdgcn_mfma_i32_16x16x32_i8(a0, b, acc, 0, 0, 0);
-        }
+        mfma_step<KT>(y0, y1, t0, t1, tot);
     }
 
     // lane l holds D[(l / 16) * 4 + i][l mod 16] of every (shift, tile)
