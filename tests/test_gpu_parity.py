@@ -394,3 +394,22 @@ def test_small_groups_every_shape(O, pirmod, prf):
                 got = out.cpu().numpy().view(np.uint32)
                 want = O.answer_batch(K, Tn, nthreads=cpu_threads())
                 assert (got == want).all(), (rows, dim, nk)
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+@pytest.mark.parametrize("rows,dim", [(1 << 20, 64), ((1 << 20) - 3, 40)])
+def test_sixteen_keys_full_size_dense(O, pirmod, prf, rows, dim):
+    """Sixteen keys on a dense 2^20-row table (the small-batch kernel with the
+    product on the matrix cores), also with a ragged row count and rows of 40
+    words: every per-server answer against the oracle's full evaluation."""
+    import torch
+
+    seed = 31 + prf + dim
+    T = W.make_table(rows, dim, seed)
+    alphas = W.uniform_indices(rows, 16, seed)
+    K, _ = O.gen_batch(20, alphas, W.key_seeds(16, seed), prf_id=prf)
+    out = pirmod.answer(torch.from_numpy(K).cuda(), T.cuda(), prf=prf)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    want = O.answer_batch(K, T.numpy().view(np.uint32), nthreads=cpu_threads())
+    assert (got == want).all()
