@@ -61,6 +61,7 @@ VALU_FULL_NODE, VALU_BOTTOM_NODE = VALU_NODE["aes128"]
 LOOKUPS_FULL_NODE, LOOKUPS_BOTTOM_NODE = LOOKUPS_NODE["aes128"]
 PEAK_INT32_OPS = 256 * 64 * 2.4e9   # CUs x VALU lanes per clock x clock: 39.3 T int32 op/s
 PEAK_LDS_LOOKUPS = 256 * 32 * 2.4e9  # CUs x 128 B/clk of LDS reads / 4 B: 19.7 T lookups/s
+HBM_PEAK_GBS = 8000.0                # MI355X HBM3E, published
 KERNEL_SOURCES = ["paper_2301_10904_amd/csrc/pir_kernels.h", "paper_2301_10904_amd/csrc/aes_gfx950.h",
                   "paper_2301_10904_amd/csrc/aes_tables.h", "paper_2301_10904_amd/csrc/chacha_gfx950.h",
                   "paper_2301_10904_amd/csrc/quad_gfx950.h"]
@@ -410,9 +411,15 @@ def other_modes(args):
         k1 = keys[:1].contiguous()
         o1 = torch.empty((1, dim), dtype=torch.int32, device=dev)
         sec1, ms1 = time_launches(lambda: pir.answer(k1, T, o1, prf=prf), 20, 3)
+        # one key streams the whole table once: HBM-bound (algorithmic bytes = the table)
+        p50 = percentile(ms1, 50)
+        gbs = rows * dim * 4 / (p50 * 1e-3) / 1e9
         line.update(value=res[4096]["server_qps"], batches=res,
-                    single_query={"qps": round(1 / sec1, 1), "p50_ms": round(percentile(ms1, 50), 3),
-                                  "p99_ms": round(percentile(ms1, 99), 3)},
+                    single_query={"qps": round(1 / sec1, 1), "p50_ms": round(p50, 3),
+                                  "p99_ms": round(percentile(ms1, 99), 3),
+                                  "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                               "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
+                                               "bytes": rows * dim * 4}},
                     config={"workload": "one table 2^25 x 64 uint32 (8 GiB) resident, 1024/2048/4096 keys"})
     elif args.mode == "pbr":
         line.update(pbr_sweep(args))
