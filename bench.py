@@ -165,6 +165,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="keys of the workload the oracle answers for the CPU baseline (x8 for ChaCha20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-prf-ceiling", dest="prf_ceiling", action="store_false",
+                    help="skip the PRF-engine ceiling (libpir_engine.so) in the default line")
     ap.add_argument("--mode", default="batch",
                     choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull", "sizes", "batchsweep"],
                     help="batch: 2^20 x 64, 512 pairs (the default line); small: 2^14 x 16, one pair; "
@@ -280,6 +282,13 @@ def main():
                 "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(prf),
                 "kernel": "k_pir_waves", "valu_ops_per_launch": valu_ops,
                 "avg_launch_ms": round(kern_s * 1e3, 4), "kernel_digest": kernel_digest()}
+    # the fused kernel's tree nodes per second against the PRF engine alone
+    # (the same node mix, tables and workgroups, nothing else), and the
+    # contraction's multiply-adds per second
+    nodes = B * ((1 << n) - 1)
+    prf_ceiling = prf_engine_rate(prf, nodes / kern_s) if args.prf_ceiling else None
+    contraction = {"macs_per_s": round(B * rows * dim / kern_s, 1), "unit": "uint32 MAC/s",
+                   "note": "int8 matrix cores on balanced base-256 digits, exact mod 2^32"}
     lds_rate = lookups / kern_s / 1e12
     roofline_lds = {"achieved": round(lds_rate, 3), "peak": round(PEAK_LDS_LOOKUPS / 1e12, 3),
                     "unit": "T lookups/s", "frac": round(lds_rate * 1e12 / PEAK_LDS_LOOKUPS, 4),
@@ -320,11 +329,48 @@ def main():
         "exact": recon_ok,
         "roofline": roofline,
         "roofline_lds": roofline_lds,
+        "prf_ceiling": prf_ceiling,
+        "contraction": contraction,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
     if not recon_ok:
         sys.exit(1)
+
+
+def prf_engine_rate(prf: str, kernel_nodes_per_s: float) -> dict:
+    """Tree nodes per second of the PRF engine alone (libpir_engine.so: every
+    lane evaluates a chain of full and bottom nodes, as a walk does, with the
+    same PRF code, LDS tables and 512-lane workgroups) and the fused kernel's
+    rate as a fraction of it."""
+    import ctypes
+
+    import torch
+
+    from paper_2301_10904_amd import build as pbuild
+
+    if not pbuild.ENGINE_LIB.exists():
+        raise FileNotFoundError(f"{pbuild.ENGINE_LIB} is not built; run __graft_entry__.build()")
+    lib = ctypes.CDLL(str(pbuild.ENGINE_LIB))
+    lib.pir_prf_engine.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                   ctypes.c_void_p]
+    lib.pir_prf_engine.restype = ctypes.c_int
+    blocks, steps = 2048, 512  # 2^30 nodes, about the 1024-key launch
+    out = torch.empty(blocks * 512, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    pid = 0 if prf == "aes128" else 1
+
+    def run():
+        rc = lib.pir_prf_engine(pid, blocks, steps, ctypes.c_void_p(out.data_ptr()),
+                                ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"pir_prf_engine failed: {rc}")
+
+    _, ms = time_launches(run, 5, 1)
+    nodes_s = blocks * 512 * steps * 2 / (float(np.median(ms)) * 1e-3)
+    return {"engine_nodes_per_s": round(nodes_s, 1), "kernel_nodes_per_s": round(kernel_nodes_per_s, 1),
+            "frac": round(kernel_nodes_per_s / nodes_s, 4),
+            "engine": "k_prf_engine: 2048 x 512 lanes, 512 steps of one full and one bottom node each"}
 
 
 def time_launches(fn, steps, warmup):

@@ -10,6 +10,9 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libpir.so"
 SOURCES = ["pir_device.hip", "pir_host.cpp"]
+# a measurement kernel (the PRF-engine ceiling), kept out of the PIR library
+ENGINE_LIB = PKG / "libpir_engine.so"
+ENGINE_SOURCES = ["prf_engine.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
@@ -24,12 +27,13 @@ def hipcc() -> str:
     return str(Path(rocm) / "bin" / "hipcc")
 
 
-def build_library(out: Path | None = None, extra: list[str] | None = None, verbose: bool = False) -> Path:
+def build_library(out: Path | None = None, extra: list[str] | None = None, verbose: bool = False,
+                  sources: list[str] | None = None) -> Path:
     """Compile every HIP/C++ source of the library into one shared object."""
     out = Path(out) if out else LIB
     tmp = out.with_suffix(".so.tmp")
     cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), f"-I{ROOT / 'include'}", f"-I{CSRC}",
-           *[str(CSRC / s) for s in SOURCES], "-o", str(tmp)]
+           *[str(CSRC / s) for s in (sources or SOURCES)], "-o", str(tmp)]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
@@ -39,5 +43,11 @@ def build_library(out: Path | None = None, extra: list[str] | None = None, verbo
     return out
 
 
+def build_engine(verbose: bool = False) -> Path:
+    """The PRF-engine measurement kernel (used by bench.py only)."""
+    return build_library(ENGINE_LIB, verbose=verbose, sources=ENGINE_SOURCES)
+
+
 if __name__ == "__main__":
     print(build_library(verbose=True))
+    print(build_engine(verbose=True))

@@ -188,7 +188,7 @@ __device__ __forceinline__ uint32_t xcd_block()
     return x * per + (x < extra ? x : extra) + k;
 }
 
-__global__ void k_fill_zero(uint32_t *out, size_t count)
+__global__ __attribute__((unused)) void k_fill_zero(uint32_t *out, size_t count)
 {
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;

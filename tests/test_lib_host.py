@@ -279,3 +279,21 @@ def test_plan_rejects_bad_arguments(lib):
                  (0, 1, 1 << 10, 257), (0, 1, (1 << 32) + 1, 8)):
         assert lib.pir_plan(*args, ctypes.byref(out)) == pir.PIR_EINVAL, args
     assert lib.pir_plan(0, 1, 1 << 10, 8, None) == pir.PIR_EINVAL
+
+
+def test_prf_engine_library_exports_and_rejects_bad_arguments():
+    """The PRF-engine measurement kernel (bench.py's PRF ceiling) is a library
+    of its own; bad arguments are refused before anything is launched."""
+    import ctypes
+
+    from paper_2301_10904_amd import build as pbuild
+
+    if not pbuild.ENGINE_LIB.exists():
+        pytest.skip("libpir_engine.so not built")
+    eng = ctypes.CDLL(str(pbuild.ENGINE_LIB))
+    eng.pir_prf_engine.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                   ctypes.c_void_p]
+    eng.pir_prf_engine.restype = ctypes.c_int
+    assert eng.pir_prf_engine(0, 1, 1, None, None) == -1        # no output buffer
+    assert eng.pir_prf_engine(2, 1, 1, ctypes.c_void_p(16), None) == -1  # unknown PRF
+    assert eng.pir_prf_engine(0, 0, 1, ctypes.c_void_p(16), None) == -1  # no workgroups
