@@ -338,7 +338,7 @@ def main():
         sys.exit(1)
 
 
-def prf_engine_rate(prf: str, kernel_nodes_per_s: float) -> dict:
+def prf_engine_rate(prf: str, kernel_nodes_per_s: float) -> dict | None:
     """Tree nodes per second of the PRF engine alone (libpir_engine.so: every
     lane evaluates a chain of full and bottom nodes, as a walk does, with the
     same PRF code, LDS tables and 512-lane workgroups) and the fused kernel's
@@ -350,7 +350,10 @@ def prf_engine_rate(prf: str, kernel_nodes_per_s: float) -> dict:
     from paper_2301_10904_amd import build as pbuild
 
     if not pbuild.ENGINE_LIB.exists():
-        raise FileNotFoundError(f"{pbuild.ENGINE_LIB} is not built; run __graft_entry__.build()")
+        # a measurement aid only: the line is still valid without it
+        print(f"{pbuild.ENGINE_LIB} is not built (run __graft_entry__.build()); prf_ceiling omitted",
+              file=sys.stderr, flush=True)
+        return None
     lib = ctypes.CDLL(str(pbuild.ENGINE_LIB))
     lib.pir_prf_engine.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                    ctypes.c_void_p]
