@@ -166,14 +166,18 @@ static int wave_class(uint32_t dim)
 
 // Which kernel answers one table: the wave kernel (int8 matrix cores, up to 16
 // keys per wave) from a batch size on that depends on the PRF and the domain,
-// else the small-batch kernel, which also takes rows wider than 64 words.  A
-// wave item costs the same for 9..16 keys.  Every lane of the wave kernel
-// walks its own path from the root, while the small-batch kernel shares the
-// path above its chunks; for small domains that repeated descent outweighs
-// the matrix-core contraction.  Measured at 9..16 keys: on 2^20 x 64 rows the
-// small-batch kernel takes 0.49 ms against 0.59 (AES-128), on 2^22 rows 1.90
-// against 1.60 ms; with ChaCha20 the wave kernel wins from 17 keys at both
-// sizes (1.05 against 1.12 ms at 2^20), and with either PRF from 24 keys.
+// else the small-batch kernel, which also takes rows wider than 64 words.
+// Every lane of the wave kernel walks its own path from the root, while the
+// small-batch kernel shares the path above its chunks; for small domains that
+// repeated descent outweighs everything else.  Measured (p50 per call, rows of
+// 64 words): 9..16 keys on 2^20 rows take 0.42 ms on the small-batch kernel
+// against 0.59 on the wave kernel with AES-128, 0.46 against 1.02 with
+// ChaCha20; on 2^22 rows 1.60 against 1.56 ms with AES-128.  From 17 keys the
+// wave kernel is as fast or faster with AES-128 (0.81 against 0.82 ms at 17,
+// 1.45 against 1.61 at 64 keys on 2^20 rows).  With ChaCha20 the small-batch
+// kernel would still win at 19..64 keys on 2^20 rows (0.91 against 1.03 ms at
+// 32), but a second group holding only 1 or 2 keys runs 26% longer than one
+// with more, for a reason not found, so ChaCha20 also hands over at 17.
 static uint32_t wave_min_keys(uint32_t prf_id, uint32_t n)
 {
     if (prf_id == PIR_PRF_CHACHA20)

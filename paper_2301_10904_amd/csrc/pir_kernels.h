@@ -1,8 +1,8 @@
 // pir_kernels.h -- device side of the fused full-domain DPF evaluation x table
 // product on gfx950: the PRF policies, the small-batch kernel k_pir_fused and
 // the batched kernel k_pir_waves, with the work-item structures their launchers
-// (pir_device.hip) fill in.  Included once, by pir_device.hip; everything here
-// has internal linkage.
+// (pir_device.hip) fill in.  Included by pir_device.hip (and by the
+// measurement kernel in prf_engine.hip); everything here has internal linkage.
 //
 // For every key q of a batch, one server computes (paper section 3.1)
 //     out[q][k] = sum_j Eval(k_q, j) * T[j][k]   (mod 2^32),
@@ -25,7 +25,9 @@
 //     all Q keys over its own subtrees, so it passes the shares through a
 //     private LDS slot and immediately multiplies them into the table rows
 //     of those subtrees (coalesced 256-byte rows); no workgroup barrier is
-//     needed in the walk.
+//     needed in the walk.  With 16 keys and rows of at most 64 words the
+//     shares are the matrix cores' operand directly (mfma_step), as in the
+//     batched kernel.
 //   * Partial sums are reduced across waves in LDS and added with 32-bit
 //     atomics into out; integer addition mod 2^32 makes the result exact and
 //     independent of the order.
