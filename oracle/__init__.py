@@ -58,6 +58,8 @@ def _bind(lib):
         "or_eval_level": (ctypes.c_int, [u8p, ctypes.c_uint32, u8p]),
         "or_eval_full": (ctypes.c_int, [u8p, u32p]),
         "or_answer": (ctypes.c_int, [u8p, u32p, ctypes.c_uint64, ctypes.c_uint32, u32p]),
+        "or_answer_slice": (ctypes.c_int, [u8p, ctypes.c_uint64, u32p, ctypes.c_uint64, ctypes.c_uint32,
+                                           u32p]),
         "or_answer_batch": (ctypes.c_int, [u8p, ctypes.c_uint32, ctypes.c_size_t, u32p,
                                            ctypes.c_uint64, ctypes.c_uint32, u32p,
                                            ctypes.c_int]),
@@ -212,6 +214,17 @@ class Oracle:
         if self.lib.or_answer(_u8(np.ascontiguousarray(key)), _u32(table), rows, dim,
                               _u32(out)):
             raise ValueError("or_answer rejected its arguments")
+        return out
+
+    def answer_slice(self, key: np.ndarray, table: np.ndarray, row0: int) -> np.ndarray:
+        """One GPU's share of a row-sharded table (section 3.2.7): table row i
+        holds index row0 + i."""
+        table = np.ascontiguousarray(table, dtype=np.uint32)
+        rows, dim = table.shape
+        out = np.zeros(dim, np.uint32)
+        if self.lib.or_answer_slice(_u8(np.ascontiguousarray(key)), row0, _u32(table), rows, dim,
+                                    _u32(out)):
+            raise ValueError("or_answer_slice rejected its arguments")
         return out
 
     def answer_batch(self, keys: np.ndarray, table: np.ndarray,

@@ -299,6 +299,29 @@ int or_answer(const uint8_t *key, const uint32_t *table, uint64_t rows,
     return 0;
 }
 
+/* One GPU's share of a table whose rows are split over several GPUs (section
+ * 3.2.7): each GPU evaluates the DPF on its own subset of the indices and the
+ * partial results are summed.  Here the subset is the slice row0 .. row0 +
+ * rows - 1, table row i holding index row0 + i, every share by point
+ * evaluation:  ans[k] = sum_{i<rows} Eval(key, row0 + i) * T[i][k] mod 2^32. */
+int or_answer_slice(const uint8_t *key, uint64_t row0, const uint32_t *table, uint64_t rows,
+                    uint32_t dim, uint32_t *ans)
+{
+    if (!key_ok(key) || !table || !ans || dim == 0 || rows == 0)
+        return -1;
+    uint32_t n = key[2];
+    if (n > 62 || row0 + rows > ((uint64_t)1 << n) || row0 + rows < row0)
+        return -1;
+    for (uint32_t k = 0; k < dim; k++)
+        ans[k] = 0;
+    for (uint64_t i = 0; i < rows; i++) {
+        const uint32_t y = or_eval_point(key, row0 + i);
+        for (uint32_t k = 0; k < dim; k++)
+            ans[k] += y * table[i * dim + k]; /* uint32 wraps mod 2^32 */
+    }
+    return 0;
+}
+
 struct batch_job {
     const uint8_t *keys;
     uint32_t nkeys;

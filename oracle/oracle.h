@@ -80,6 +80,11 @@ int or_eval_full(const uint8_t *key, uint32_t *shares);
 /* ans[k] = sum_{j<rows} Eval(key, j) * T[j][k] mod 2^32; rows <= 2^n. */
 int or_answer(const uint8_t *key, const uint32_t *table, uint64_t rows,
               uint32_t dim, uint32_t *ans);
+/* A row slice (one GPU's share of a row-sharded table, section 3.2.7):
+ * ans[k] = sum_{i<rows} Eval(key, row0 + i) * T[i][k] mod 2^32, shares by
+ * point evaluation; row0 + rows <= 2^n. */
+int or_answer_slice(const uint8_t *key, uint64_t row0, const uint32_t *table, uint64_t rows,
+                    uint32_t dim, uint32_t *ans);
 /* Same, for nkeys keys at byte stride `stride`, spread over nthreads threads
  * (one key per task; the arithmetic per key is or_answer's). */
 int or_answer_batch(const uint8_t *keys, uint32_t nkeys, size_t stride,

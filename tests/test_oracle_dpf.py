@@ -227,3 +227,44 @@ def test_answer_rejects_bad_shapes(O):
     bad[0] = 2  # unknown key version
     with pytest.raises(ValueError):
         O.answer(bad, np.zeros((16, 2), np.uint32))
+
+
+@pytest.mark.parametrize("n,shards,dim", [(6, 2, 3), (9, 8, 5), (11, 4, 16), (8, 64, 2)])
+def test_answer_slices_sum_to_the_answer(O, n, shards, dim):
+    """Row sharding (section 3.2.7): the slices' answers, each by point
+    evaluation, equal an independent numpy product over the full evaluation
+    and sum to the whole table's answer mod 2^32; the two servers' slice
+    answers reconstruct T[alpha] in the slice holding alpha and zero in every
+    other slice."""
+    rows = 1 << n
+    size = rows // shards
+    rng = np.random.default_rng([n, shards, dim])
+    T = rng.integers(0, 2**32, (rows, dim), dtype=np.uint64).astype(np.uint32)
+    alpha = int(rng.integers(0, rows))
+    k0, k1 = O.gen(n, alpha, 1, seed_for(n, shards, dim))
+    y0 = O.eval_full(k0)
+    total = np.zeros(dim, np.uint64)
+    for s in range(shards):
+        r0 = s * size
+        a0 = O.answer_slice(k0, T[r0:r0 + size], r0)
+        a1 = O.answer_slice(k1, T[r0:r0 + size], r0)
+        assert (a0 == numpy_answer(y0[r0:r0 + size], T[r0:r0 + size])).all()
+        want = T[alpha] if r0 <= alpha < r0 + size else np.zeros(dim, np.uint32)
+        assert (O.reconstruct(a0, a1) == want).all(), s
+        total = (total + a0) & 0xFFFFFFFF
+    assert (total.astype(np.uint32) == O.answer(k0, T)).all()
+
+
+def test_answer_slice_ragged_and_rejects(O):
+    """An unaligned, ragged slice still follows the definition; a slice past
+    the domain is refused."""
+    n, dim = 7, 4
+    rng = np.random.default_rng(71)
+    T = rng.integers(0, 2**32, (1 << n, dim), dtype=np.uint64).astype(np.uint32)
+    k0, _ = O.gen(n, 100, 1, seed_for(71))
+    y = O.eval_full(k0)
+    for r0, cnt in ((0, 1), (5, 17), (100, 28), (127, 1)):
+        got = O.answer_slice(k0, T[r0:r0 + cnt], r0)
+        assert (got == numpy_answer(y[r0:r0 + cnt], T[r0:r0 + cnt])).all(), (r0, cnt)
+    with pytest.raises(ValueError):
+        O.answer_slice(k0, T[:2], 127)  # indices 127, 128: past 2^7

@@ -46,6 +46,8 @@ MUTANTS = {
                              "or_prf_by(0, parent, (uint64_t)c, p);"),
     "bins_first_row_not_scaled": ("dpf_ref.c", "uint64_t first = b << jb->bin_log;", "uint64_t first = b;"),
     "bins_keys_bin_major": ("dpf_ref.c", "uint64_t b = i % jb->n_bins;", "uint64_t b = i / jb->n_clients;"),
+    "slice_ignores_offset": ("dpf_ref.c", "const uint32_t y = or_eval_point(key, row0 + i);",
+                             "const uint32_t y = or_eval_point(key, i);"),
     "answer_skips_last_row": ("dpf_ref.c", "for (uint64_t j = 0; j < rows; j++)\n        for (uint32_t k",
                               "for (uint64_t j = 0; j + 1 < rows; j++)\n        for (uint32_t k"),
 }
