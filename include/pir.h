@@ -121,6 +121,28 @@ int pir_answer_prf(uint32_t prf_id, const uint8_t *d_keys, uint32_t n_keys,
                    uint32_t key_stride, const uint32_t *d_table, uint64_t rows,
                    uint32_t dim, uint32_t *d_out, void *stream);
 
+/* One GPU's share of a table whose rows are split over several GPUs (paper
+ * section 3.2.7: each GPU evaluates the DPF on its own subset of the indices,
+ * and the partial answers are summed, which is exact because the reduction
+ * is a sum).  Keys of domain 2^n are evaluated on the indices row0 .. row0 +
+ * rows - 1 only, table row i holding index row0 + i:
+ *     d_out[q][k] = sum_{i<rows} Eval(key_q, row0 + i) * T[i][k]   mod 2^32,
+ * so the outputs of slices that cover 0 .. L - 1, added mod 2^32, equal
+ * pir_answer_prf over the whole table.  Each lane descends from the key's
+ * root to the slice, which costs the n - m extra path nodes per key that
+ * splitting over 2^(n-m) GPUs implies.
+ *   n          the keys' domain, 1..32; every key header must carry it
+ *   row0       first index of the slice; with m = max(1, ceil(log2 rows)) it
+ *              must be a multiple of 2^m (the slice lies in one aligned
+ *              subtree; equal slices of 2^(n-g) rows for 2^g GPUs do), and
+ *              row0 + rows <= 2^n
+ *   d_table    the slice: row-major uint32 [rows][dim], rows >= 1
+ * Other arguments, bad keys and errors as for pir_answer_prf; PIR_EINVAL also
+ * for an unaligned or out-of-domain slice. */
+int pir_answer_slice(uint32_t prf_id, uint32_t n, uint64_t row0, const uint8_t *d_keys, uint32_t n_keys,
+                     uint32_t key_stride, const uint32_t *d_table, uint64_t rows, uint32_t dim,
+                     uint32_t *d_out, void *stream);
+
 /* One table of a multi-table call. */
 typedef struct {
     const uint32_t *d_table; /* row-major uint32 [rows][dim] in HBM */

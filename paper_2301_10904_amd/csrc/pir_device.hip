@@ -86,7 +86,8 @@ static uint32_t wave_height(uint64_t n_bins, uint64_t bin_rows, uint64_t groups,
 // Work plan of a wave-kernel launch over `count` tasks: fills h, n_groups,
 // chunks_per_bin and item_begin of every task and returns the number of wave
 // items (0 if it reaches 2^31).  The subtree height h is at most what the path
-// registers allow (HMAX3) and n - 2 (a bin holds four subtrees); a single
+// registers allow (HMAX3) and m - 2 (a bin, or the aligned subtree holding a
+// table slice, of height m holds four subtrees); a single
 // table gets the height of wave_height(), a launch of several tables the
 // largest (the tables together fill the GPU).
 static uint64_t plan_waves(WaveTask *ts, uint32_t count)
@@ -97,7 +98,10 @@ static uint64_t plan_waves(WaveTask *ts, uint32_t count)
         t.n_groups = (t.n_keys + 15) / 16;
         const uint64_t bin_rows = std::min<uint64_t>(t.rows, (uint64_t)1 << t.n);
         auto chunks_per_bin = [&](uint32_t hh) { return (bin_rows + ((uint64_t)4 << hh) - 1) / ((uint64_t)4 << hh); };
-        const uint32_t hmax = std::min<uint32_t>(HMAX3, t.n - 2);
+        // a slice of a table lies in an aligned subtree of height m < n, and a
+        // lane's subtree must lie in it too; whole tables and bins have m = n
+        const uint32_t m = std::min<uint32_t>(t.n, bin_rows <= 2 ? 1 : ceil_log2(bin_rows));
+        const uint32_t hmax = std::min<uint32_t>(HMAX3, m - 2);
         const uint32_t h = count == 1 ? wave_height(t.n_bins, bin_rows, t.n_groups, t.n, hmax) : hmax;
         t.h = h;
         t.chunks_per_bin = (uint32_t)chunks_per_bin(h);
@@ -199,17 +203,21 @@ struct FusedPlan {
     uint64_t grid;
 };
 
-static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32_t n)
+// n is the keys' domain; the rows lie in an aligned subtree of height m <= n
+// from index row0 (m = n and row0 = 0 for a whole table), and chunks of 2^H
+// rows, H <= m, stay inside it.
+static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32_t n, uint32_t m, uint64_t row0)
 {
-    FusedPlan p;
+    FusedPlan p{};
     p.Q = n_keys >= QMAX ? QMAX : (uint32_t)1 << ceil_log2(n_keys);
     const uint32_t lgS_max = ceil_log2(NT / p.Q);
     const uint32_t groups = (n_keys + p.Q - 1) / p.Q;
     const uint32_t want = ceil_log2((512 + groups - 1) / groups); // about one round of workgroup slots
-    uint32_t H = n > want ? n - want : 1;
+    uint32_t H = m > want ? m - want : 1;
     H = std::min(H, lgS_max + (uint32_t)HMAX);
-    H = std::max(H, std::min(n, lgS_max + 1));
-    H = std::min(H, n);
+    H = std::max(H, std::min(m, lgS_max + 1));
+    H = std::min(H, m);
+    p.g.row0 = row0;
     p.g.n = n;
     p.g.H = H;
     p.g.lgS = std::min(lgS_max, H - 1);
@@ -221,28 +229,33 @@ static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32
     return p;
 }
 
-// Validates one table's call and enqueues its kernels.
+// Validates a call over the table rows holding indices row0 .. row0 + rows -
+// 1 of keys of domain 2^n (a whole table: row0 = 0, n = ceil(log2 rows)) and
+// enqueues its kernels.
 template <class PRF>
-static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, const uint32_t *d_table,
-                      uint64_t rows, uint32_t dim, uint32_t *d_out, hipStream_t st)
+static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, uint32_t n, uint64_t row0,
+                        const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out, hipStream_t st)
 {
     if (n_keys == 0)
         return PIR_OK;
     if (!d_keys || !d_table || !d_out || rows == 0 || dim == 0)
         return PIR_EINVAL;
-    if (rows > ((uint64_t)1 << PIR_MAX_LOG_DOMAIN) || dim > PIR_MAX_DIM)
+    if (n == 0 || n > PIR_MAX_LOG_DOMAIN || dim > PIR_MAX_DIM)
         return PIR_EINVAL;
-    const uint32_t n = rows <= 2 ? 1 : ceil_log2(rows);
+    const uint32_t m = rows <= 2 ? 1 : ceil_log2(rows); // the slice's aligned subtree
+    if (m > n || row0 % ((uint64_t)1 << m) || row0 + rows > ((uint64_t)1 << n))
+        return PIR_EINVAL;
     if (key_stride % 16 || key_stride < dpf_key_size(n) || ((uintptr_t)d_keys % 16) ||
         ((uintptr_t)d_table % 4) || ((uintptr_t)d_out % 4))
         return PIR_EINVAL;
 
-    if (use_wave_kernel(PRF::id, n_keys, n, dim)) {
-        WaveTask t;
+    if (use_wave_kernel(PRF::id, n_keys, m, dim)) {
+        WaveTask t{};
         t.table = d_table;
         t.keys = d_keys;
         t.out = d_out;
         t.rows = rows;
+        t.row0 = row0;
         t.dim = dim;
         t.n_keys = n_keys;
         t.n = n;
@@ -250,7 +263,7 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
         return launch_waves<PRF>(&t, 1, key_stride, st);
     }
 
-    const FusedPlan p = plan_fused(n_keys, rows, dim, n);
+    const FusedPlan p = plan_fused(n_keys, rows, dim, n, m, row0);
     if (p.grid >= ((uint64_t)1 << 31))
         return PIR_ENOMEM;
     const Geometry &g = p.g;
@@ -269,6 +282,17 @@ static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_strid
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? PIR_OK : fail_hip(e);
+}
+
+// One whole table.
+template <class PRF>
+static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, const uint32_t *d_table,
+                      uint64_t rows, uint32_t dim, uint32_t *d_out, hipStream_t st)
+{
+    if (rows == 0 || rows > ((uint64_t)1 << PIR_MAX_LOG_DOMAIN))
+        return n_keys == 0 ? PIR_OK : PIR_EINVAL;
+    const uint32_t n = rows <= 2 ? 1 : ceil_log2(rows);
+    return answer_range<PRF>(d_keys, n_keys, key_stride, n, 0, d_table, rows, dim, d_out, st);
 }
 
 template <class PRF>
@@ -305,7 +329,7 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
         const uint32_t n = T.rows <= 2 ? 1 : ceil_log2(T.rows);
         const int c = wave_class(T.dim);
         if (n >= 3 && c >= 0) { // several tables share a launch, so even small batches go to waves
-            WaveTask w;
+            WaveTask w{};
             w.table = T.d_table;
             w.keys = kp;
             w.out = op;
@@ -362,7 +386,7 @@ static int answer_bins(const pir_bins_t *tables, uint32_t n_tables, const uint8_
         out_off += (size_t)T.n_clients * n_bins * T.dim;
         if (T.n_clients == 0)
             continue;
-        WaveTask w;
+        WaveTask w{};
         w.table = T.d_table;
         w.keys = kp;
         w.out = op;
@@ -418,7 +442,7 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
         out->bfs_levels = 0;
         return PIR_OK;
     }
-    const FusedPlan p = plan_fused(n_keys, rows, dim, n);
+    const FusedPlan p = plan_fused(n_keys, rows, dim, n, n, 0);
     if (p.grid >= ((uint64_t)1 << 31))
         return PIR_ENOMEM;
     out->kernel = PIR_KERNEL_SMALL_BATCH;
@@ -451,6 +475,18 @@ int pir_answer_prf(uint32_t prf_id, const uint8_t *d_keys, uint32_t n_keys, uint
         return answer_one<AesPrf>(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, (hipStream_t)stream);
     if (prf_id == PIR_PRF_CHACHA20)
         return answer_one<ChaChaPrf>(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, (hipStream_t)stream);
+    return PIR_EINVAL;
+}
+
+int pir_answer_slice(uint32_t prf_id, uint32_t n, uint64_t row0, const uint8_t *d_keys, uint32_t n_keys,
+                     uint32_t key_stride, const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out,
+                     void *stream)
+{
+    const hipStream_t st = (hipStream_t)stream;
+    if (prf_id == PIR_PRF_AES128)
+        return answer_range<AesPrf>(d_keys, n_keys, key_stride, n, row0, d_table, rows, dim, d_out, st);
+    if (prf_id == PIR_PRF_CHACHA20)
+        return answer_range<ChaChaPrf>(d_keys, n_keys, key_stride, n, row0, d_table, rows, dim, d_out, st);
     return PIR_EINVAL;
 }
 

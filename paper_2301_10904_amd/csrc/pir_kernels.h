@@ -199,6 +199,7 @@ __global__ __attribute__((unused)) void k_fill_zero(uint32_t *out, size_t count)
 }
 
 struct Geometry {
+    uint64_t row0;     // index of table row 0 in the key domain (a slice; 0 for a whole table)
     uint32_t n;        // log2 of the key domain
     uint32_t H;        // rows per item = 2^H
     uint32_t lgS;      // lanes used per key = 2^lgS (lgS < H)
@@ -353,7 +354,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             const KeyView K{keys + (size_t)(grp * Q + qk) * stride};
             uint32_t s = sm.u.bfs[qk].w[w];
             for (uint32_t d = 1; d <= dtop; d++) {
-                const uint32_t c = (uint32_t)(row_base >> (g.n - d)) & 1u;
+                const uint32_t c = (uint32_t)((g.row0 + row_base) >> (g.n - d)) & 1u;
                 const uint32_t t = quad_first(s) & 1u;
                 const uint32_t cw = *reinterpret_cast<const uint32_t *>(K.p + 32 + 64 * (size_t)(d - 1) + 32 * t +
                                                                         16 * c + 4 * w);
@@ -365,7 +366,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         const KeyView K{keys + (size_t)(grp * Q + tid) * stride};
         Seed s = sm.u.bfs[tid];
         for (uint32_t d = 1; d <= dtop; d++)
-            s = child_on_path(P, K, s, d, (uint32_t)(row_base >> (g.n - d)) & 1u);
+            s = child_on_path(P, K, s, d, (uint32_t)((g.row0 + row_base) >> (g.n - d)) & 1u);
         sm.u.bfs[tid] = s;
     }
     __syncthreads();
@@ -688,6 +689,7 @@ struct WaveTask {
     const uint8_t *keys;   // this table's first key
     uint32_t *out;         // this table's first answer word
     uint64_t rows;
+    uint64_t row0;                   // index of table row 0 in the key domain (a slice; else 0)
     uint32_t dim, n_keys, n, h, n_groups, item_begin;
     uint32_t n_bins, chunks_per_bin; // n_keys counts clients
 };
@@ -749,7 +751,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (active) {
         node = K.root();
         for (uint32_t d = 1; d + h <= g.n; d++)
-            node = child_on_path(P, K, node, d, (uint32_t)(lane_row0 >> (g.n - d)) & 1u);
+            node = child_on_path(P, K, node, d, (uint32_t)((g.row0 + lane_row0) >> (g.n - d)) & 1u);
     }
     const uint32_t d0 = g.n - h;
     Seed right[HMAX3];

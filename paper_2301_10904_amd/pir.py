@@ -21,7 +21,7 @@ PRF_AES128, PRF_CHACHA20 = 0, 1  # key byte 3
 PRFS = {"aes128": PRF_AES128, "chacha20": PRF_CHACHA20}
 
 # the exported C ABI, as declared in include/pir.h
-EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_prf",
+EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_prf", "pir_answer_slice",
            "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_plan", "pir_reconstruct",
            "pir_check_status", "pir_strerror", "pir_last_hip_error")
 KERNEL_WAVES, KERNEL_SMALL_BATCH = 1, 2
@@ -78,6 +78,10 @@ def load(path: Path | None = None):
     lib.pir_answer_prf.argtypes = [ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint32,
                                    ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p,
                                    ctypes.c_void_p]
+    lib.pir_answer_slice.restype = ctypes.c_int
+    lib.pir_answer_slice.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_void_p,
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
     lib.pir_answer_multi_prf.restype = ctypes.c_int
     lib.pir_answer_multi_prf.argtypes = [ctypes.c_uint32, ctypes.POINTER(PirTable), ctypes.c_uint32,
                                          ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p,
@@ -185,6 +189,28 @@ def _check_dev(t, name, dtypes):
         raise TypeError(f"{name} has dtype {t.dtype}")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+
+
+def answer_slice(keys, table, n, row0, out=None, stream=None, prf=PRF_AES128):
+    """One GPU's share of a row-sharded table (pir_answer_slice): keys of
+    domain 2^n evaluated on the indices row0 .. row0 + rows - 1 only, table
+    row i holding index row0 + i; summing the slices' outputs mod 2^32 gives
+    answer() over the whole table.  Arguments otherwise as for answer()."""
+    import torch
+
+    lib = load()
+    _check_dev(keys, "keys", (torch.uint8,))
+    _check_dev(table, "table", (torch.int32, torch.uint32))
+    B, stride = keys.shape
+    rows, dim = table.shape
+    if out is None:
+        out = torch.empty((B, dim), dtype=torch.int32, device=table.device)
+    _check_dev(out, "out", (torch.int32, torch.uint32))
+    if tuple(out.shape) != (B, dim):
+        raise ValueError("out must be [B, dim]")
+    _check(lib.pir_answer_slice(prf_id(prf), n, row0, keys.data_ptr(), B, stride, table.data_ptr(), rows, dim,
+                                out.data_ptr(), _stream_handle(stream)), "pir_answer_slice")
+    return out
 
 
 def answer(keys, table, out=None, stream=None, prf=PRF_AES128):

@@ -413,3 +413,65 @@ def test_sixteen_keys_full_size_dense(O, pirmod, prf, rows, dim):
     got = out.cpu().numpy().view(np.uint32)
     want = O.answer_batch(K, T.numpy().view(np.uint32), nthreads=cpu_threads())
     assert (got == want).all()
+
+
+SLICE_CASES = [
+    # n, shards, dim, keys: both kernels, wide and narrow rows, tiny slices
+    (12, 4, 16, 3), (14, 8, 64, 40), (16, 2, 7, 20), (13, 16, 33, 1), (10, 64, 4, 17), (15, 4, 130, 5),
+]
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+@pytest.mark.parametrize("n,shards,dim,nkeys", SLICE_CASES)
+def test_slices_sum_to_the_answer(O, pirmod, prf, n, shards, dim, nkeys):
+    """Row sharding (section 3.2.7) on one GPU: each slice's per-server answer
+    against the oracle's, and the slices' answers summed mod 2^32 against the
+    library's own whole-table answer for the same keys."""
+    import torch
+
+    rows, seed = 1 << n, n * 100 + shards + prf
+    size = rows // shards
+    T = W.make_table(rows, dim, seed)
+    Tn = T.numpy().view(np.uint32)
+    Td = T.cuda()
+    alphas = W.uniform_indices(rows, nkeys, seed)
+    K, _ = O.gen_batch(n, alphas, W.key_seeds(nkeys, seed), prf_id=prf)
+    keys = torch.from_numpy(K).cuda()
+    full = pirmod.answer(keys, Td, prf=prf)
+    total = torch.zeros_like(full)
+    ys = [O.eval_full(k) for k in K]
+    for s in range(shards):
+        r0 = s * size
+        part = pirmod.answer_slice(keys, Td[r0:r0 + size], n, r0, prf=prf)
+        torch.cuda.synchronize()
+        got = part.cpu().numpy().view(np.uint32)
+        for q in range(nkeys):
+            want = ((ys[q][r0:r0 + size, None].astype(np.uint64) * Tn[r0:r0 + size]).sum(0) & 0xFFFFFFFF)
+            assert (got[q] == want.astype(np.uint32)).all(), (s, q)
+        total += part  # int32 addition wraps mod 2^32
+    torch.cuda.synchronize()
+    assert (total.cpu().numpy() == full.cpu().numpy()).all()
+    # one slice also straight from the oracle's definition (point evaluation)
+    r0 = (shards // 2) * size
+    want = O.answer_slice(K[0], Tn[r0:r0 + size], r0)
+    got = pirmod.answer_slice(keys[:1].contiguous(), Td[r0:r0 + size], n, r0, prf=prf)
+    assert (got.cpu().numpy().view(np.uint32)[0] == want).all()
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+def test_ragged_slice(O, pirmod, prf):
+    """A slice shorter than its aligned subtree (the last GPU's share of a
+    table whose rows are not a power of two)."""
+    import torch
+
+    n, dim, r0, cnt = 12, 24, 3072, 1000
+    T = W.make_table(r0 + cnt, dim, 5 + prf)
+    Tn = T.numpy().view(np.uint32)
+    for nk in (3, 18):  # the small-batch and the wave kernel
+        alphas = W.uniform_indices(r0 + cnt, nk, 5)
+        K, _ = O.gen_batch(n, alphas, W.key_seeds(nk, 5), prf_id=prf)
+        got = pirmod.answer_slice(torch.from_numpy(K).cuda(), T[r0:].contiguous().cuda(), n, r0, prf=prf)
+        torch.cuda.synchronize()
+        got = got.cpu().numpy().view(np.uint32)
+        for q in sorted({0, nk // 2, nk - 1}):
+            assert (got[q] == O.answer_slice(K[q], Tn[r0:], r0)).all(), (nk, q)

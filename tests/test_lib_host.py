@@ -131,6 +131,35 @@ def test_answer_validation_without_gpu(lib):
     assert lib.pir_answer_prf(2, fake, 1, ks, fake, 1024, 4, fake, None) == pir.PIR_EINVAL
 
 
+def test_answer_slice_validation_without_gpu(lib):
+    """Row slices (one GPU's share of a row-sharded table): the slice must lie
+    in one aligned subtree inside the keys' domain; every rejected call returns
+    before touching the HIP runtime."""
+    fake = ctypes.c_void_p(0x1000)
+    ks = pir.key_size(20)
+    ok = dict(n=20, row0=3 << 12, keys=fake, nk=1, ks=ks, table=fake, rows=1 << 12, dim=4, out=fake)
+
+    def call(**kw):
+        a = {**ok, **kw}
+        return lib.pir_answer_slice(pir.PRF_AES128, a["n"], a["row0"], a["keys"], a["nk"], a["ks"], a["table"],
+                                    a["rows"], a["dim"], a["out"], None)
+
+    bad = [dict(n=0), dict(n=33),
+           dict(rows=(1 << 20) + 1),                 # slice taller than the domain
+           dict(row0=(3 << 12) + 1),                 # not on a 2^12 boundary
+           dict(row0=1 << 11),                       # 2^11 is not a multiple of 2^12
+           dict(row0=(1 << 20) - (1 << 12), rows=(1 << 12) + 1),  # past 2^n (and unaligned height)
+           dict(row0=1 << 20),                       # starts past the domain
+           dict(ks=pir.key_size(12)),                # stride for a 12-level key, the keys have 20
+           dict(keys=None), dict(table=None), dict(out=None), dict(rows=0), dict(dim=0), dict(dim=257)]
+    for b in bad:
+        assert call(**b) == pir.PIR_EINVAL, b
+    # rows = 1: the slice's subtree has height 1, so row0 must be even
+    assert call(rows=1, row0=5) == pir.PIR_EINVAL
+    assert call(nk=0) == pir.PIR_OK  # no keys: nothing to do
+    assert lib.pir_answer_slice(2, 20, 0, fake, 1, ks, fake, 1 << 12, 4, fake, None) == pir.PIR_EINVAL
+
+
 def test_answer_multi_validation_without_gpu(lib):
     fake = 0x1000
     ks = pir.key_size(12)
