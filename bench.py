@@ -174,14 +174,16 @@ def main():
     ap.add_argument("--no-prf-ceiling", dest="prf_ceiling", action="store_false",
                     help="skip the PRF-engine ceiling (libpir_engine.so) in the default line")
     ap.add_argument("--mode", default="batch",
-                    choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull", "sizes", "batchsweep"],
+                    choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull", "sizes", "batchsweep",
+                             "shards"],
                     help="batch: 2^20 x 64, 512 pairs (the default line); small: 2^14 x 16, one pair; "
                          "multi: 8 tables 2^16..2^23 x 32, ragged Zipf batches in one call; "
                          "large: 2^25 x 64 (8 GiB), 512..2048 pairs; serve: Poisson request loop over 4 tables; "
                          "pbr: partial batch retrieval on 2^20 x 64, bins of 2^10..2^14; "
                          "hotfull: hot table + full table with fixed query budgets; "
                          "sizes: 2^14, 2^20, 2^22 rows x 64 (the table sizes of the paper's GPU/CPU comparison); "
-                         "batchsweep: latency and throughput for 1..1024 keys per call on 2^20 x 64")
+                         "batchsweep: latency and throughput for 1..1024 keys per call on 2^20 x 64; "
+                         "shards: one GPU's share of the 2^25 x 64 table split over 2, 4, 8 GPUs (row slices)")
     ap.add_argument("--prf", default="aes128", choices=["aes128", "chacha20"],
                     help="the DPF tree's PRF (section 3.2.6): AES-128 (default) or ChaCha20")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
@@ -476,6 +478,8 @@ def other_modes(args):
                                                "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
                                                "bytes": rows * dim * 4}},
                     config={"workload": "one table 2^25 x 64 uint32 (8 GiB) resident, 1024/2048/4096 keys"})
+    elif args.mode == "shards":
+        line.update(shards_run(args))
     elif args.mode == "pbr":
         line.update(pbr_sweep(args))
     elif args.mode == "sizes":
@@ -487,6 +491,54 @@ def other_modes(args):
     else:
         line.update(serve_sweep(args))
     print(json.dumps(line), flush=True)
+
+
+def shards_run(args):
+    """Row sharding (section 3.2.7) at its real shape on one GPU: the 2^25 x 64
+    table (8 GiB) cut into G = 2, 4, 8 slices; one GPU's share is one slice
+    with every key (domain 2^25).  Reports the slice launch time (what each of
+    G GPUs would take, before the final sum over GPUs) against the whole
+    table's, and checks that the 8 slices' answers add up, mod 2^32, to the
+    whole table's answer and reconstruct every queried row."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    prf = args.prf
+    n, dim, pairs, seed = 25, 64, 512, 6
+    rows = 1 << n
+    T = W.make_table(rows, dim, seed, device=dev)
+    a = W.uniform_indices(rows, pairs, seed)
+    K0, K1 = pir.gen_batch(n, a, W.key_seeds(pairs, seed), prf=prf)
+    keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
+    B = 2 * pairs
+    full = torch.empty((B, dim), dtype=torch.int32, device=dev)
+    sec_full, _ = time_launches(lambda: pir.answer(keys, T, full, prf=prf), 2, 1)
+    runs = []
+    for G in (2, 4, 8):
+        size = rows // G
+        part = torch.empty((B, dim), dtype=torch.int32, device=dev)
+        sec, _ = time_launches(lambda: pir.answer_slice(keys, T[:size], n, 0, part, prf=prf), 3, 1)
+        runs.append({"gpus": G, "slice_rows": size, "slice_ms": round(sec * 1e3, 2),
+                     "share_of_whole": round(sec / sec_full, 4), "ideal_share": round(1 / G, 4),
+                     "projected_server_qps": round(B / sec, 1)})
+    # exactness of the 8-way split: the slices' answers add up to the whole table's
+    size = rows // 8
+    total = torch.zeros((B, dim), dtype=torch.int32, device=dev)
+    for s in range(8):
+        total += pir.answer_slice(keys, T[s * size:(s + 1) * size], n, s * size, prf=prf)
+    torch.cuda.synchronize()
+    got = total.cpu().numpy().view(np.uint32)
+    exact = bool((got == full.cpu().numpy().view(np.uint32)).all())
+    rec = ((got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF).astype(np.uint32)
+    exact &= bool((rec == W.table_rows_np(a, dim, seed)).all())
+    return {"prf": prf, "value": runs[-1]["projected_server_qps"], "unit": "server queries/s per 8 GPUs (projected)",
+            "exact": exact, "whole_table_ms": round(sec_full * 1e3, 2), "shards": runs,
+            "config": {"workload": "one table 2^25 x 64 uint32 (8 GiB) split into 2, 4, 8 row slices; "
+                                   "1024 keys (both servers) of domain 2^25 on one slice = one GPU's share; "
+                                   "the final sum over GPUs (a 256 KiB reduction) is not included"}}
 
 
 def batch_sweep(args):
