@@ -303,9 +303,24 @@ __device__ __forceinline__ void mfma_step(uint32_t y0, uint32_t y1, const uint32
     }
 }
 
+// 16 bytes of a table row; STREAM: without allocating in the caches (a
+// table read once per call and larger than the memory-side cache)
+template <bool STREAM>
+__device__ __forceinline__ uint4 row_load4(const uint32_t *p)
+{
+    if constexpr (STREAM) {
+        typedef unsigned v4u __attribute__((ext_vector_type(4)));
+        const v4u v = __builtin_nontemporal_load(reinterpret_cast<const v4u *>(p));
+        return make_uint4(v.x, v.y, v.z, v.w);
+    } else {
+        return *reinterpret_cast<const uint4 *>(p);
+    }
+}
+
 // Q keys per group (Q <= QMAX); KCH column chunks of 64 (dim <= 64 KCH);
-// VEC4: dim is a multiple of 4 (16-byte row segments are aligned).
-template <class PRF, int Q, int KCH, bool VEC4>
+// VEC4: dim is a multiple of 4 (16-byte row segments are aligned); STREAM:
+// table rows are read with row_load4<true> (single keys on large tables).
+template <class PRF, int Q, int KCH, bool VEC4, bool STREAM>
 __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ keys, uint32_t n_keys,
                                                   uint32_t stride, const uint32_t *__restrict__ table,
                                                   uint64_t rows, uint32_t dim, uint32_t *__restrict__ out,
@@ -549,7 +564,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
                             const uint32_t col = 64 * c + 4 * cg;
                             if (VEC4) {
                                 const uint4 x =
-                                    col < dim ? *reinterpret_cast<const uint4 *>(trow + col) : make_uint4(0, 0, 0, 0);
+                                    col < dim ? row_load4<STREAM>(trow + col) : make_uint4(0, 0, 0, 0);
                                 tv[u][c][0] = ok ? x.x : 0u;
                                 tv[u][c][1] = ok ? x.y : 0u;
                                 tv[u][c][2] = ok ? x.z : 0u;
