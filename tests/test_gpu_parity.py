@@ -475,3 +475,21 @@ def test_ragged_slice(O, pirmod, prf):
         got = got.cpu().numpy().view(np.uint32)
         for q in sorted({0, nk // 2, nk - 1}):
             assert (got[q] == O.answer_slice(K[q], Tn[r0:], r0)).all(), (nk, q)
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+@pytest.mark.parametrize("dim", [100, 200])
+def test_single_key_streamed_wide_rows(O, pirmod, prf, dim):
+    """A single key on a dense table above 256 MiB (rows read with
+    non-temporal loads) with rows of 100 and 200 words (two and four column
+    chunks): the per-server answer against the oracle."""
+    import torch
+
+    rows, seed = 1 << 20, 61 + dim + prf
+    T = W.make_table(rows, dim, seed)
+    alphas = W.uniform_indices(rows, 1, seed)
+    K, _ = O.gen_batch(20, alphas, W.key_seeds(1, seed), prf_id=prf)
+    out = pirmod.answer(torch.from_numpy(K).cuda(), T.cuda(), prf=prf)
+    torch.cuda.synchronize()
+    want = O.answer_batch(K, T.numpy().view(np.uint32), nthreads=1)
+    assert (out.cpu().numpy().view(np.uint32) == want).all()
