@@ -178,7 +178,7 @@ int pir_answer_multi_prf(uint32_t prf_id, const pir_table_t *tables, uint32_t n_
  * the cost of one full-table query.  Which entry each bin serves, and dummy
  * keys for bins it does not need, are the client's business. */
 #define PIR_BINS_MIN_LOG 3  /* bins of at least 8 rows   */
-#define PIR_BINS_MAX_DIM 64 /* rows of at most 64 words  */
+#define PIR_BINS_MAX_DIM 128 /* rows of at most 128 words */
 typedef struct {
     const uint32_t *d_table; /* row-major uint32 [rows][dim] in HBM, 4-byte aligned */
     uint64_t rows;           /* 1 <= rows <= 2^32 */
@@ -207,7 +207,7 @@ int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables
  * launches nothing and needs no GPU.  PIR_EINVAL for an unknown prf_id, no
  * keys, or sizes pir_answer rejects; PIR_ENOMEM where pir_answer would. */
 #define PIR_KERNEL_WAVES 1       /* batched: up to 16 keys per wave, int8 matrix cores */
-#define PIR_KERNEL_SMALL_BATCH 2 /* small batches (or rows > 64 words): 512-lane workgroups */
+#define PIR_KERNEL_SMALL_BATCH 2 /* small batches (or rows > 128 words): 512-lane workgroups */
 typedef struct {
     uint32_t kernel;              /* PIR_KERNEL_* */
     uint32_t n;                   /* key domain: ceil(log2 rows), at least 1 */

@@ -154,7 +154,9 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipSt
     const dim3 grid((uint32_t)((items + NW3 - 1) / NW3));
     const uint32_t dim = ts[0].dim;
 #define PIR_LAUNCH_WAVES(KT, VEC) hipLaunchKernelGGL((k_pir_waves<PRF, KT, VEC>), grid, dim3(NT3), 0, st, W, key_stride)
-    if (dim == 64)
+    if (dim > 64)
+        PIR_LAUNCH_WAVES(8, false);
+    else if (dim == 64)
         PIR_LAUNCH_WAVES(4, true);
     else if (dim == 32)
         PIR_LAUNCH_WAVES(2, true);
@@ -180,12 +182,13 @@ static int wave_class(uint32_t dim)
     if (dim < 16) return 3;
     if (dim < 32) return 4;
     if (dim <= 64) return 5;
+    if (dim <= 128) return 6;
     return -1;
 }
 
 // Which kernel answers one table: the wave kernel (int8 matrix cores, up to 16
 // keys per wave) from a batch size on that depends on the PRF and the domain,
-// else the small-batch kernel, which also takes rows wider than 64 words.
+// else the small-batch kernel, which also takes rows wider than 128 words.
 // Every lane of the wave kernel walks its own path from the root, while the
 // small-batch kernel shares the path above its chunks; for small domains that
 // repeated descent outweighs everything else.  Measured (p50 per call, rows of
@@ -205,7 +208,7 @@ static uint32_t wave_min_keys(uint32_t prf_id, uint32_t n)
 }
 static bool use_wave_kernel(uint32_t prf_id, uint32_t n_keys, uint32_t n, uint32_t dim)
 {
-    return n_keys >= wave_min_keys(prf_id, n) && n >= 3 && dim <= 64;
+    return n_keys >= wave_min_keys(prf_id, n) && n >= 3 && dim <= 128;
 }
 
 // Work plan of the small-batch kernel: Q keys per workgroup, chunks of 2^H
@@ -331,7 +334,7 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
     }
     // tables the wave kernel takes go out grouped by column class, up to
     // MAX_TASKS per launch; the rest one by one
-    std::vector<WaveTask> cls[6];
+    std::vector<WaveTask> cls[7];
     size_t key_off = 0, out_off = 0;
     for (uint32_t t = 0; t < n_tables; t++) {
         const pir_table_t &T = tables[t];
@@ -390,7 +393,7 @@ static int answer_bins(const pir_bins_t *tables, uint32_t n_tables, const uint8_
             ((uintptr_t)T.d_table % 4) || ((uintptr_t)d_out % 4))
             return PIR_EINVAL;
     }
-    std::vector<WaveTask> cls[6];
+    std::vector<WaveTask> cls[7];
     size_t key_off = 0, out_off = 0;
     for (uint32_t t = 0; t < n_tables; t++) {
         const pir_bins_t &T = tables[t];

@@ -715,7 +715,7 @@ struct WaveTasks {
 };
 
 template <class PRF, int KT, bool VEC>
-__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_waves(const WaveTasks tasks,
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 : 4))) void k_pir_waves(const WaveTasks tasks,
                                                                                            uint32_t stride)
 {
     __shared__ uint32_t tab[PRF::TAB_WORDS ? PRF::TAB_WORDS : 1];

@@ -25,7 +25,7 @@ EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_p
            "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_plan", "pir_reconstruct",
            "pir_check_status", "pir_strerror", "pir_last_hip_error")
 KERNEL_WAVES, KERNEL_SMALL_BATCH = 1, 2
-BINS_MIN_LOG, BINS_MAX_DIM = 3, 64
+BINS_MIN_LOG, BINS_MAX_DIM = 3, 128
 
 _lib = None
 
@@ -292,7 +292,7 @@ def n_bins(rows: int, bin_log: int) -> int:
 def answer_bins(tables, client_counts, bin_logs, keys, out=None, stream=None, prf=PRF_AES128):
     """Partial batch retrieval, server side (section 4.1), over one or more tables.
 
-    tables        : list of int32/uint32 device tensors [rows_t, dim_t] (dim_t <= 64)
+    tables        : list of int32/uint32 device tensors [rows_t, dim_t] (dim_t <= 128)
     client_counts : clients per table; each sends one key per bin of its table
     bin_logs      : bins of 2^bin_logs[t] rows per table
     keys          : uint8 device tensor, per table client-major: key (c, b) of

@@ -54,6 +54,8 @@ CASES = [
     # rows, dim, bin_log, clients: one group, partial groups, several groups, ragged last bin
     (1 << 12, 16, 8, 1), (1 << 12, 64, 10, 5), (3000, 7, 6, 17), (5000, 32, 9, 40),
     (1 << 14, 64, 12, 16), (777, 3, 3, 2), (1 << 13, 33, 13, 20),
+    # rows of 65..128 words (eight column tiles per lane)
+    (1 << 12, 128, 9, 6), (3000, 100, 7, 17), (2000, 65, 11, 3),
 ]
 
 

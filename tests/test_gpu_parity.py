@@ -418,6 +418,7 @@ def test_sixteen_keys_full_size_dense(O, pirmod, prf, rows, dim):
 SLICE_CASES = [
     # n, shards, dim, keys: both kernels, wide and narrow rows, tiny slices
     (12, 4, 16, 3), (14, 8, 64, 40), (16, 2, 7, 20), (13, 16, 33, 1), (10, 64, 4, 17), (15, 4, 130, 5),
+    (14, 4, 100, 20),
 ]
 
 
@@ -493,3 +494,62 @@ def test_single_key_streamed_wide_rows(O, pirmod, prf, dim):
     torch.cuda.synchronize()
     want = O.answer_batch(K, T.numpy().view(np.uint32), nthreads=1)
     assert (out.cpu().numpy().view(np.uint32) == want).all()
+
+
+WIDE_WAVE_CASES = [
+    # rows, dim, keys: rows of 65..128 words on the wave kernel (eight column
+    # tiles), one and several key groups, ragged row counts and key groups
+    (1 << 12, 65, 40), (3001, 100, 18), ((1 << 14) + 5, 128, 33), ((1 << 13) - 1, 127, 17),
+]
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+@pytest.mark.parametrize("rows,dim,nkeys", WIDE_WAVE_CASES)
+def test_wide_rows_wave_kernel(O, pirmod, prf, rows, dim, nkeys):
+    """Batches on rows of 65 to 128 words, which the wave kernel takes with
+    eight column tiles per lane: every per-server answer against the oracle
+    and every reconstruction against T[alpha]."""
+    import torch
+
+    assert pirmod.plan(nkeys, rows, dim, prf=prf)["kernel"] == pirmod.KERNEL_WAVES
+    seed = rows + dim + nkeys + prf
+    n = log_domain(rows)
+    T = W.make_table(rows, dim, seed)
+    alphas = W.uniform_indices(rows, nkeys, seed)
+    alphas[0] = rows - 1
+    K0, K1 = O.gen_batch(n, alphas, W.key_seeds(nkeys, seed), prf_id=prf)
+    keys = np.concatenate([K0, K1])
+    out = pirmod.answer(torch.from_numpy(keys).cuda(), T.cuda(), prf=prf)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    Tn = T.numpy().view(np.uint32)
+    want = O.answer_batch(keys, Tn, nthreads=cpu_threads())
+    assert (got == want).all()
+    for i, a in enumerate(alphas):
+        assert (O.reconstruct(got[i], got[nkeys + i]) == Tn[a]).all(), i
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+def test_full_size_2p20_x128_batch64(O, pirmod, prf):
+    """2^20 rows of 128 words (512 MiB, the 512-byte entries of the paper's
+    larger tables) with 32 key pairs on the wave kernel: every reconstruction
+    equals T[alpha]; per-server answers against the oracle on a sample."""
+    import torch
+
+    rows, dim, pairs, seed = 1 << 20, 128, 32, 71 + prf
+    T = W.make_table(rows, dim, seed, device="cuda")
+    alphas = W.uniform_indices(rows, pairs, seed)
+    K0, K1 = O.gen_batch(20, alphas, W.key_seeds(pairs, seed), prf_id=prf)
+    keys = np.concatenate([K0, K1])
+    out = pirmod.answer(torch.from_numpy(keys).cuda(), T, prf=prf)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    Trows = W.table_rows_np(alphas, dim, seed)
+    for p in range(pairs):
+        assert (O.reconstruct(got[p], got[pairs + p]) == Trows[p]).all(), p
+    Tn = T.cpu().numpy().view(np.uint32)
+    sample = np.array([0, 17, 31, 32, 63])
+    want = O.answer_batch(keys[sample], Tn, nthreads=cpu_threads())
+    assert (got[sample] == want).all()
+    del T
+    torch.cuda.empty_cache()

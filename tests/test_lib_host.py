@@ -178,7 +178,7 @@ def test_answer_bins_validation_without_gpu(lib):
     ks = pir.key_size(10)
     ok = pir.PirBins(fake, 1 << 14, 16, 4, 10)
     bad = [
-        pir.PirBins(fake, 1 << 14, 65, 4, 10),      # rows wider than 64 words
+        pir.PirBins(fake, 1 << 14, 129, 4, 10),     # rows wider than 128 words
         pir.PirBins(fake, 1 << 14, 16, 4, 2),       # bins below 8 rows
         pir.PirBins(fake, 0, 16, 4, 10),            # no rows
         pir.PirBins(None, 1 << 14, 16, 4, 10),      # null table
@@ -271,7 +271,9 @@ def test_plan_small_wave_batches_fill_the_gpu():
 
 
 def test_plan_kernel_choice():
-    assert pir.plan(1024, 1 << 20, 65)["kernel"] == pir.KERNEL_SMALL_BATCH   # rows wider than 64 words
+    assert pir.plan(1024, 1 << 20, 129)["kernel"] == pir.KERNEL_SMALL_BATCH  # rows wider than 128 words
+    assert pir.plan(1024, 1 << 20, 65)["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(1024, 1 << 20, 128)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(16, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH     # AES-128, up to 2^20 rows: 16 keys
     assert pir.plan(17, 1 << 20, 64)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(8, (1 << 20) + 1, 64)["kernel"] == pir.KERNEL_SMALL_BATCH  # larger domains: 8 keys
@@ -289,7 +291,7 @@ def test_plan_kernel_choice():
         n = max(1, (rows - 1).bit_length())
         assert p["n"] == n
         if p["kernel"] == pir.KERNEL_WAVES:
-            assert keys >= (17 if n <= 20 else 9) and dim <= 64 and n >= 3
+            assert keys >= (17 if n <= 20 else 9) and dim <= 128 and n >= 3
             assert p["descent_levels"] + p["subtree_log"] == n
             chunks = -(-rows // p["rows_per_item"])
             assert p["items"] == chunks * -(-keys // 16)
