@@ -173,6 +173,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-prf-ceiling", dest="prf_ceiling", action="store_false",
                     help="skip the PRF-engine ceiling (libpir_engine.so) in the default line")
+    ap.add_argument("--no-peaks", dest="peaks", action="store_false",
+                    help="skip the measured peaks (libpir_engine.so probes) in the default line")
     ap.add_argument("--mode", default="batch",
                     choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull", "sizes", "batchsweep",
                              "shards"],
@@ -301,6 +303,13 @@ def main():
     roofline_lds = {"achieved": round(lds_rate, 3), "peak": round(PEAK_LDS_LOOKUPS / 1e12, 3),
                     "unit": "T lookups/s", "frac": round(lds_rate * 1e12 / PEAK_LDS_LOOKUPS, 4),
                     "lookups_per_launch": lookups} if lookups else None
+    # the same rates against what the probes measure on this GPU (the
+    # published peaks above stay the roofline's denominators)
+    peaks = measured_peaks() if args.peaks else None
+    if peaks:
+        roofline["frac_of_measured"] = round(achieved / peaks["valu_T_lane_ops"], 4)
+        if roofline_lds:
+            roofline_lds["frac_of_measured"] = round(lds_rate / peaks["lds_T_lookups"], 4)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -339,11 +348,88 @@ def main():
         "roofline_lds": roofline_lds,
         "prf_ceiling": prf_ceiling,
         "contraction": contraction,
+        "measured_peaks": peaks,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)
     if not recon_ok:
         sys.exit(1)
+
+
+def engine_lib(what: str):
+    """The measurement library (libpir_engine.so: the PRF engine and the peak
+    probes), or None with a note on stderr if it is not built."""
+    import ctypes
+
+    from paper_2301_10904_amd import build as pbuild
+
+    if not pbuild.ENGINE_LIB.exists():
+        # a measurement aid only: the line is still valid without it
+        print(f"{pbuild.ENGINE_LIB} is not built (run __graft_entry__.build()); {what} omitted",
+              file=sys.stderr, flush=True)
+        return None
+    lib = ctypes.CDLL(str(pbuild.ENGINE_LIB))
+    lib.pir_prf_engine.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                   ctypes.c_void_p]
+    lib.pir_prf_engine.restype = ctypes.c_int
+    lib.pir_peak_probe.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
+                                   ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
+    lib.pir_peak_probe.restype = ctypes.c_int
+    return lib
+
+
+# Peak probes (libpir_engine.so, pir_peak_probe): kind, workgroups, iterations
+# per lane, lanes per workgroup, and the work one lane-iteration counts for.
+# HBM: a 4 GiB buffer streamed once with 16-byte non-temporal loads.
+PEAK_PROBES = {
+    "valu": (1, 2048, 8192, 256, 16),          # 16 v_xor_b32 (lane-ops)
+    "lds": (2, 512, 16384, 512, 8),            # 8 ds_read_b32 lookups
+    "mfma_i8": (3, 2048, 8192, 256, 8 * 32768 / 64),      # 8 16x16x64 MFMAs per wave (ops per lane)
+    "mfma_i8_k32": (4, 2048, 8192, 256, 8 * 16384 / 64),  # 8 16x16x32 MFMAs per wave
+}
+PEAK_NAMES = {"valu": "valu_T_lane_ops", "lds": "lds_T_lookups", "mfma_i8": "mfma_i8_TOPs",
+              "mfma_i8_k32": "mfma_i8_16x16x32_TOPs"}
+HBM_PROBE_WORDS = 1 << 30
+
+
+def measured_peaks() -> dict | None:
+    """What this GPU delivers for HBM reads, int32 VALU ops, LDS lookups in the
+    AES table layout and int8 matrix-core ops, each from a plain probe loop
+    (median of 5 timed calls), next to the published figures."""
+    import ctypes
+
+    import torch
+
+    lib = engine_lib("measured_peaks")
+    if lib is None:
+        return None
+    stream = torch.cuda.current_stream()
+    res = {}
+    out = torch.empty(2048 * 512, dtype=torch.int32, device="cuda")
+    buf = torch.full((HBM_PROBE_WORDS,), 3, dtype=torch.int32, device="cuda")
+
+    def probe(kind, blocks, iters, src=None):
+        ptr = ctypes.c_void_p(src.data_ptr()) if src is not None else None
+        rc = lib.pir_peak_probe(kind, blocks, iters, ptr, src.numel() if src is not None else 0,
+                                ctypes.c_void_p(out.data_ptr()), ctypes.c_void_p(stream.cuda_stream))
+        if rc != 0:
+            raise RuntimeError(f"pir_peak_probe({kind}) failed: {rc}")
+
+    _, ms = time_launches(lambda: probe(0, 2048, 0, buf), 5, 1)
+    res["hbm_read_GBs"] = round(HBM_PROBE_WORDS * 4 / (float(np.median(ms)) * 1e-3) / 1e9, 1)
+    ok = int(out[:2048 * 256].to(torch.int64).sum().item()) % (1 << 32) == (3 * HBM_PROBE_WORDS) % (1 << 32)
+    del buf
+    for name, (kind, blocks, iters, lanes, per_lane) in PEAK_PROBES.items():
+        _, ms = time_launches(lambda: probe(kind, blocks, iters), 5, 1)
+        rate = blocks * lanes * iters * per_lane / (float(np.median(ms)) * 1e-3)
+        res[PEAK_NAMES[name]] = round(rate / 1e12, 3)
+    res["published"] = {"hbm_read_GBs": HBM_PEAK_GBS, "valu_T_lane_ops": round(PEAK_INT32_OPS / 1e12, 3),
+                        "lds_T_lookups": round(PEAK_LDS_LOOKUPS / 1e12, 3), "mfma_i8_TOPs": 5000.0}
+    res["hbm_checksum_ok"] = ok
+    res["probes"] = ("pir_peak_probe: 4 GiB non-temporal 16-byte reads; 16 v_xor_b32 chains per lane; "
+                     "8 ds_read_b32 chains per lane in the AES table layout (64 KiB, 512 lanes); "
+                     "8 v_mfma_i32_16x16x64_i8 (and, separately, 16x16x32) accumulators per wave")
+    return res
 
 
 def prf_engine_rate(prf: str, kernel_nodes_per_s: float) -> dict | None:
@@ -355,17 +441,9 @@ def prf_engine_rate(prf: str, kernel_nodes_per_s: float) -> dict | None:
 
     import torch
 
-    from paper_2301_10904_amd import build as pbuild
-
-    if not pbuild.ENGINE_LIB.exists():
-        # a measurement aid only: the line is still valid without it
-        print(f"{pbuild.ENGINE_LIB} is not built (run __graft_entry__.build()); prf_ceiling omitted",
-              file=sys.stderr, flush=True)
+    lib = engine_lib("prf_ceiling")
+    if lib is None:
         return None
-    lib = ctypes.CDLL(str(pbuild.ENGINE_LIB))
-    lib.pir_prf_engine.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
-                                   ctypes.c_void_p]
-    lib.pir_prf_engine.restype = ctypes.c_int
     blocks, steps = 2048, 512  # 2^30 nodes, about the 1024-key launch
     out = torch.empty(blocks * 512, dtype=torch.int32, device="cuda")
     stream = torch.cuda.current_stream()
@@ -471,12 +549,17 @@ def other_modes(args):
         # one key streams the whole table once: HBM-bound (algorithmic bytes = the table)
         p50 = percentile(ms1, 50)
         gbs = rows * dim * 4 / (p50 * 1e-3) / 1e9
+        del T
+        torch.cuda.empty_cache()
+        peaks = measured_peaks() if args.peaks else None
+        hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+               "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": rows * dim * 4}
+        if peaks:
+            hbm["measured_read_GBs"] = peaks["hbm_read_GBs"]
+            hbm["frac_of_measured"] = round(gbs / peaks["hbm_read_GBs"], 4)
         line.update(value=res[4096]["server_qps"], batches=res,
                     single_query={"qps": round(1 / sec1, 1), "p50_ms": round(p50, 3),
-                                  "p99_ms": round(percentile(ms1, 99), 3),
-                                  "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
-                                               "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4),
-                                               "bytes": rows * dim * 4}},
+                                  "p99_ms": round(percentile(ms1, 99), 3), "roofline": hbm},
                     config={"workload": "one table 2^25 x 64 uint32 (8 GiB) resident, 1024/2048/4096 keys"})
     elif args.mode == "shards":
         line.update(shards_run(args))

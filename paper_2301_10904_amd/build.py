@@ -10,9 +10,9 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 LIB = PKG / "libpir.so"
 SOURCES = ["pir_device.hip", "pir_host.cpp"]
-# a measurement kernel (the PRF-engine ceiling), kept out of the PIR library
+# measurement kernels (the PRF-engine ceiling, the peak probes), kept out of the PIR library
 ENGINE_LIB = PKG / "libpir_engine.so"
-ENGINE_SOURCES = ["prf_engine.hip"]
+ENGINE_SOURCES = ["prf_engine.hip", "peak_probes.hip"]
 
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",

@@ -328,3 +328,27 @@ def test_prf_engine_library_exports_and_rejects_bad_arguments():
     assert eng.pir_prf_engine(0, 1, 1, None, None) == -1        # no output buffer
     assert eng.pir_prf_engine(2, 1, 1, ctypes.c_void_p(16), None) == -1  # unknown PRF
     assert eng.pir_prf_engine(0, 0, 1, ctypes.c_void_p(16), None) == -1  # no workgroups
+
+
+def test_peak_probes_export_and_reject_bad_arguments():
+    """The peak probes (bench.py's measured peaks) live in the same measurement
+    library; bad arguments are refused before anything is launched."""
+    import ctypes
+
+    from paper_2301_10904_amd import build as pbuild
+
+    if not pbuild.ENGINE_LIB.exists():
+        pytest.skip("libpir_engine.so not built")
+    eng = ctypes.CDLL(str(pbuild.ENGINE_LIB))
+    f = eng.pir_peak_probe
+    f.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_uint64,
+                  ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    buf, out = ctypes.c_void_p(0x1000), ctypes.c_void_p(0x2000)
+    assert f(0, 1, 1, buf, 1024, None, None) == -1                    # no output buffer
+    assert f(5, 1, 1, buf, 1024, out, None) == -1                     # unknown probe
+    assert f(1, 0, 1, buf, 1024, out, None) == -1                     # no workgroups
+    assert f(0, 1, 1, None, 1024, out, None) == -1                    # read probe without input
+    assert f(0, 1, 1, buf, 0, out, None) == -1                        # empty input
+    assert f(0, 1, 1, buf, 1022, out, None) == -1                     # not whole 16-byte units
+    assert f(0, 1, 1, ctypes.c_void_p(0x1004), 1024, out, None) == -1  # misaligned input
