@@ -383,7 +383,7 @@ def engine_lib(what: str):
 # HBM: a 4 GiB buffer streamed once with 16-byte non-temporal loads.
 PEAK_PROBES = {
     "valu": (1, 2048, 8192, 256, 16),          # 16 v_xor_b32 (lane-ops)
-    "lds": (2, 512, 16384, 512, 8),            # 8 ds_read_b32 lookups
+    "lds": (2, 512, 16384, 1024, 8),           # 8 ds_read_b32 lookups
     "mfma_i8": (3, 2048, 8192, 256, 8 * 32768 / 64),      # 8 16x16x64 MFMAs per wave (ops per lane)
     "mfma_i8_k32": (4, 2048, 8192, 256, 8 * 16384 / 64),  # 8 16x16x32 MFMAs per wave
 }
@@ -427,7 +427,7 @@ def measured_peaks() -> dict | None:
                         "lds_T_lookups": round(PEAK_LDS_LOOKUPS / 1e12, 3), "mfma_i8_TOPs": 5000.0}
     res["hbm_checksum_ok"] = ok
     res["probes"] = ("pir_peak_probe: 4 GiB non-temporal 16-byte reads; 16 v_xor_b32 chains per lane; "
-                     "8 ds_read_b32 chains per lane in the AES table layout (64 KiB, 512 lanes); "
+                     "8 ds_read_b32 chains per lane in the AES table layout (64 KiB, 1024 lanes, 2 per CU); "
                      "8 v_mfma_i32_16x16x64_i8 (and, separately, 16x16x32) accumulators per wave")
     return res
 

@@ -8,7 +8,10 @@
 //   kind 2  LDS lookups: 8 independent chains of ds_read_b32 per lane, each
 //           address made from the previous load by one v_and_or_b32, in the
 //           T-table layout of the AES kernels (256-byte rows, the lane's own
-//           copy of the entry; 64 KiB, two 512-lane workgroups per CU)
+//           copy of the entry; 64 KiB per workgroup).  Two 1024-lane
+//           workgroups per CU (8 waves per SIMD): the LDS then serves more
+//           lookups than with fewer waves (two 512-lane workgroups, as in the
+//           AES kernels: about 7% fewer)
 //   kind 3  int8 matrix cores: 8 independent v_mfma_i32_16x16x64_i8
 //           accumulators per wave (the double-K form, which gfx950 runs at
 //           its full int8 rate)
@@ -23,8 +26,8 @@
 
 namespace {
 
-constexpr uint32_t PROBE_NT = 256; // lanes per workgroup (the LDS probe: 512)
-constexpr uint32_t LDS_NT = 512;
+constexpr uint32_t PROBE_NT = 256; // lanes per workgroup (the LDS probe: 1024)
+constexpr uint32_t LDS_NT = 1024;
 constexpr uint32_t LDS_WORDS = 16384; // 256 rows of 64 words
 
 __global__ __launch_bounds__(PROBE_NT) void k_peak_read(const uint32_t *__restrict__ in, uint64_t n4,
@@ -144,10 +147,10 @@ __global__ __launch_bounds__(PROBE_NT) void k_peak_mfma(uint32_t iters, uint32_t
 extern "C" {
 
 // Runs probe `kind` (0 HBM read, 1 VALU, 2 LDS, 3 int8 MFMA 16x16x64, 4 int8
-// MFMA 16x16x32) with `blocks` workgroups of 256 lanes (512 for kind 2) on
+// MFMA 16x16x32) with `blocks` workgroups of 256 lanes (1024 for kind 2) on
 // `stream`; `iters` loop iterations per lane for kinds 1..4.  Kind 0 reads in_words words at d_in
 // (16-byte aligned, in_words a multiple of 4).  d_out receives one checksum
-// word per lane: blocks * 256 words (blocks * 512 for kind 2).  Returns 0, -1
+// word per lane: blocks * 256 words (blocks * 1024 for kind 2).  Returns 0, -1
 // for bad arguments, -3 if the launch failed.
 int pir_peak_probe(uint32_t kind, uint32_t blocks, uint32_t iters, const uint32_t *d_in, uint64_t in_words,
                    uint32_t *d_out, void *stream)

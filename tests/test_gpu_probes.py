@@ -66,16 +66,16 @@ def test_valu_chains(eng, iters):
 def test_lds_chains(eng, iters):
     i = np.arange(16384, dtype=np.uint64)
     tab = ((i * 0x9E3779B9) & M32) ^ (i >> 5)
-    t = np.arange(512, dtype=np.uint64)
+    t = np.arange(1024, dtype=np.uint64)
     l4 = (t % 64 % 32) * 4
-    acc = np.zeros(512, np.uint64)
+    acc = np.zeros(1024, np.uint64)
     for c in range(8):
         v = (t * 0x85EBCA6B + c) & M32
         for _ in range(iters):
             v = tab[((v & 0xFF80) | l4) >> 2]
         acc ^= v
-    got = run(eng, 2, 2, iters, 512)
-    assert (got.reshape(2, 512) == acc.astype(np.uint32)).all()
+    got = run(eng, 2, 2, iters, 1024)
+    assert (got.reshape(2, 1024) == acc.astype(np.uint32)).all()
 
 
 def lane_bytes(words):
