@@ -200,15 +200,20 @@ static int wave_class(uint32_t dim)
 // kernel would still win at 19..64 keys on 2^20 rows (0.91 against 1.03 ms at
 // 32), but a second group holding only 1 or 2 keys runs 26% longer than one
 // with more, for a reason not found, so ChaCha20 also hands over at 17.
-static uint32_t wave_min_keys(uint32_t prf_id, uint32_t n)
+// Rows of 65..128 words: the small-batch kernel holds two column chunks and
+// at most 8 keys per workgroup (plan_fused); with ChaCha20 on 2^22 rows 9..16
+// keys then take 3.6 ms there against 2.2-2.4 ms on the wave kernel, so above
+// 2^20 rows ChaCha20 hands over at 9 keys for such rows as AES-128 does for
+// all (at 2^20 the small-batch kernel still wins: 0.92 against 0.98-1.03 ms).
+static uint32_t wave_min_keys(uint32_t prf_id, uint32_t n, uint32_t dim)
 {
     if (prf_id == PIR_PRF_CHACHA20)
-        return 17u;
+        return n > 20 && dim > 64 ? 9u : 17u;
     return n <= 20 ? 17u : 9u;
 }
 static bool use_wave_kernel(uint32_t prf_id, uint32_t n_keys, uint32_t n, uint32_t dim)
 {
-    return n_keys >= wave_min_keys(prf_id, n) && n >= 3 && dim <= 128;
+    return n_keys >= wave_min_keys(prf_id, n, dim) && n >= 3 && dim <= 128;
 }
 
 // Work plan of the small-batch kernel: Q keys per workgroup, chunks of 2^H
@@ -227,7 +232,14 @@ struct FusedPlan {
 static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32_t n, uint32_t m, uint64_t row0)
 {
     FusedPlan p{};
-    p.Q = n_keys >= QMAX ? QMAX : (uint32_t)1 << ceil_log2(n_keys);
+    p.kch = dim <= 64 ? 1 : dim <= 128 ? 2 : 4;
+    // 16 keys with two column chunks need 138-141 VGPRs, one workgroup per
+    // CU; two groups of 8 keep two (9..16 keys on 2^20 x 128: 0.92 -> 0.77
+    // ms with AES-128, 0.97 -> 0.92 with ChaCha20).  With four chunks 16
+    // keys stay faster than groups of 4 (1.45 against 1.85-2.05 ms at 200
+    // words) despite their two waves per SIMD.
+    const uint32_t qmax = p.kch == 2 ? 8u : (uint32_t)QMAX;
+    p.Q = n_keys >= qmax ? qmax : (uint32_t)1 << ceil_log2(n_keys);
     const uint32_t lgS_max = ceil_log2(NT / p.Q);
     const uint32_t groups = (n_keys + p.Q - 1) / p.Q;
     const uint32_t want = ceil_log2((512 + groups - 1) / groups); // about one round of workgroup slots
@@ -243,7 +255,6 @@ static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32
     const uint64_t chunks = (rows + ((uint64_t)1 << H) - 1) >> H;
     p.g.n_chunks = (uint32_t)std::min<uint64_t>(chunks, 0xffffffffu);
     p.grid = chunks * groups;
-    p.kch = dim <= 64 ? 1 : dim <= 128 ? 2 : 4;
     return p;
 }
 

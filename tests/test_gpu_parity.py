@@ -553,3 +553,51 @@ def test_full_size_2p20_x128_batch64(O, pirmod, prf):
     assert (got[sample] == want).all()
     del T
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+@pytest.mark.parametrize("rows,dim,nkeys", [((1 << 14) + 3, 100, 12), (4096, 128, 16), (3000, 65, 9)])
+def test_wide_rows_small_batches(O, pirmod, prf, rows, dim, nkeys):
+    """9..16 keys on rows of 65..128 words: the small-batch kernel in groups of
+    8 keys (two column chunks), the last group partial; per-server answers
+    against the oracle."""
+    import torch
+
+    p = pirmod.plan(nkeys, rows, dim, prf=prf)
+    assert p["kernel"] == pirmod.KERNEL_SMALL_BATCH and p["keys_per_item"] == 8
+    seed = 3 * rows + dim + nkeys + prf
+    n = log_domain(rows)
+    T = W.make_table(rows, dim, seed)
+    alphas = W.uniform_indices(rows, nkeys, seed)
+    K, _ = O.gen_batch(n, alphas, W.key_seeds(nkeys, seed), prf_id=prf)
+    out = pirmod.answer(torch.from_numpy(K).cuda(), T.cuda(), prf=prf)
+    torch.cuda.synchronize()
+    want = O.answer_batch(K, T.numpy().view(np.uint32), nthreads=cpu_threads())
+    assert (out.cpu().numpy().view(np.uint32) == want).all()
+
+
+def test_chacha20_wide_rows_above_2p20_on_waves(O, pirmod):
+    """ChaCha20 keys on 2^21 + 77 rows of 100 words (839 MB): 10 key pairs take
+    the wave kernel.  Every reconstruction equals T[alpha]; the per-server
+    answers of two keys against the oracle."""
+    import torch
+
+    rows, dim, pairs, seed = (1 << 21) + 77, 100, 10, 83
+    assert pirmod.plan(2 * pairs, rows, dim, prf=1)["kernel"] == pirmod.KERNEL_WAVES
+    T = W.make_table(rows, dim, seed, device="cuda")
+    alphas = W.uniform_indices(rows, pairs, seed)
+    alphas[0] = rows - 1
+    K0, K1 = O.gen_batch(22, alphas, W.key_seeds(pairs, seed), prf_id=1)
+    keys = np.concatenate([K0, K1])
+    out = pirmod.answer(torch.from_numpy(keys).cuda(), T, prf=1)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    Trows = W.table_rows_np(alphas, dim, seed)
+    for p in range(pairs):
+        assert (O.reconstruct(got[p], got[pairs + p]) == Trows[p]).all(), p
+    Tn = T.cpu().numpy().view(np.uint32)
+    sample = np.array([0, pairs + 3])
+    want = O.answer_batch(keys[sample], Tn, nthreads=cpu_threads())
+    assert (got[sample] == want).all()
+    del T
+    torch.cuda.empty_cache()

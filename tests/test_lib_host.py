@@ -280,6 +280,18 @@ def test_plan_kernel_choice():
     assert pir.plan(9, (1 << 20) + 1, 64)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(16, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH  # ChaCha20: 16
     assert pir.plan(17, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
+    # ChaCha20 on rows of 65..128 words above 2^20 rows: the wave kernel from 9 keys
+    assert pir.plan(9, (1 << 20) + 1, 100, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(8, (1 << 20) + 1, 100, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH
+    assert pir.plan(16, (1 << 20) + 1, 64, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH
+    assert pir.plan(16, 1 << 20, 128, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH
+    assert pir.plan(16, (1 << 20) + 1, 129, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH
+    # the small-batch kernel takes at most 8 keys per workgroup on rows of two column chunks
+    assert pir.plan(16, 1 << 20, 64)["keys_per_item"] == 16
+    assert pir.plan(16, 1 << 20, 65)["keys_per_item"] == 8
+    assert pir.plan(16, 1 << 20, 128)["keys_per_item"] == 8
+    assert pir.plan(5, 1 << 20, 128)["keys_per_item"] == 8
+    assert pir.plan(16, 1 << 20, 129)["keys_per_item"] == 16
     assert pir.plan(64, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH            # n = 2: too small for waves
     assert pir.plan(64, 8, 8)["kernel"] == pir.KERNEL_WAVES                  # n = 3
     rng = np.random.default_rng(5)
