@@ -207,9 +207,9 @@ def main():
         return
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU only: the server path runs on a single MI355X "
-              "(multi-GPU row sharding is a design note, not built); run with --gpus 1",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: the server path runs on a single MI355X; one GPU's "
+              "share of a row-sharded table is --mode shards, and the sum across GPUs is not built; "
+              "run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -235,14 +235,27 @@ __device__ __forceinline__ uint32_t arrange(uint32_t x)
 
 __device__ __forceinline__ long pack2(uint32_t lo, uint32_t hi) { return (long)(((uint64_t)hi << 32) | lo); }
 
-// KT consecutive words p[c0 .. c0 + KT - 1] of the row at p; columns past dim
-// read zero (VEC: dim == 16 KT, so the words are in bounds and 4 KT-byte
-// aligned).
-template <int KT, bool VEC>
-__device__ __forceinline__ void load_cols(const uint32_t *__restrict__ p, uint32_t dim, uint32_t c0,
+// The table column a lane feeds to the product as column n (= lane mod 16)
+// of 16-column tile t.  PACKED: the lane's KT tiles are KT consecutive words
+// (one vector load where the row allows it); otherwise tile t is columns
+// 16 t .. 16 t + 15, so that the 16 lanes of a row read 64 contiguous bytes
+// per word load.
+template <int KT, bool PACKED>
+__device__ __forceinline__ uint32_t col_of(uint32_t n, int t)
+{
+    return PACKED ? n * KT + (uint32_t)t : n + 16u * (uint32_t)t;
+}
+
+// The words v[t] = p[col_of<KT, PACKED>(n, t)] of the row at p, t < KT;
+// columns past dim read zero.  VEC (PACKED): dim == 16 KT, so the words are in
+// bounds and 4 KT-byte aligned, and one vector load reads them.
+template <int KT, bool VEC, bool PACKED = VEC>
+__device__ __forceinline__ void load_cols(const uint32_t *__restrict__ p, uint32_t dim, uint32_t n,
                                           uint32_t (&v)[KT])
 {
+    static_assert(PACKED || !VEC, "vector loads read packed columns");
     if (VEC) {
+        const uint32_t c0 = n * KT;
         if (KT == 4) {
             const uint4 x = *reinterpret_cast<const uint4 *>(p + c0);
             v[0] = x.x;
@@ -259,7 +272,7 @@ __device__ __forceinline__ void load_cols(const uint32_t *__restrict__ p, uint32
     } else {
 #pragma unroll
         for (int t = 0; t < KT; t++) {
-            const uint32_t c = c0 + t;
+            const uint32_t c = col_of<KT, PACKED>(n, t);
             const uint32_t x = p[c < dim ? c : dim - 1];
             v[t] = c < dim ? x : 0u;
         }
@@ -496,13 +509,12 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         if constexpr (MF) {
             const uint32_t *p0 = table + (mrow < rows ? mrow : rows - 1) * dim;
             const uint32_t *p1 = table + (mrow + 1 < rows ? mrow + 1 : rows - 1) * dim;
-            const uint32_t c0 = (lane & 15) * 4;
             if (dim == 64) {
-                load_cols<4, true>(p0, dim, c0, t0);
-                load_cols<4, true>(p1, dim, c0, t1);
+                load_cols<4, true>(p0, dim, lane & 15, t0);
+                load_cols<4, true>(p1, dim, lane & 15, t1);
             } else {
-                load_cols<4, false>(p0, dim, c0, t0);
-                load_cols<4, false>(p1, dim, c0, t1);
+                load_cols<4, false, true>(p0, dim, lane & 15, t0);
+                load_cols<4, false, true>(p1, dim, lane & 15, t1);
             }
         }
         uint32_t kst;
@@ -635,12 +647,13 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         s_acc[i] = 0;
     __syncthreads();
     if constexpr (MF) {
-        // lane l holds D[(l / 16) 4 + i][(l mod 16) 4 + t] of tile t
+        // lane l holds D[(l / 16) 4 + i][l mod 16] of tile t, table column
+        // (l mod 16) 4 + t (packed columns)
 #pragma unroll
         for (int t = 0; t < (MF ? 4 : 1); t++)
 #pragma unroll
             for (int i = 0; i < 4; i++) {
-                const uint32_t col = (lane & 15) * 4 + t;
+                const uint32_t col = col_of<4, true>(lane & 15, t);
                 if (col < dim)
                     atomicAdd(&s_acc[((lane >> 4) * 4 + i) * dim + col], (uint32_t)tot[t][i]);
             }
@@ -780,8 +793,8 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 
     for (int t = 0; t < KT; t++)
         tot[t] = v4i{0, 0, 0, 0};
 
-    // this lane's table columns: tile t, column n = lane mod 16 -> n * KT + t
-    const uint32_t col0 = (lane & 15) * KT;
+    // this lane's table columns: tile t, column n = lane mod 16 -> col_of(n, t)
+    const uint32_t ncol = lane & 15;
     const uint32_t steps = 1u << (h - 1);
     // The item's rows: a chunk of at most 4 2^h <= 2048 rows from chunk_row0,
     // read through 32-bit word offsets from the chunk's first row; a row past
@@ -797,8 +810,8 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 
         // behind this step's AES work
         const uint64_t r0 = lane_row0 + 2 * m;
         uint32_t t0[KT], t1[KT];
-        load_cols<KT, VEC>(ctab + (row_off < last_off ? row_off : last_off), dim, col0, t0);
-        load_cols<KT, VEC>(ctab + (row_off + dim < last_off ? row_off + dim : last_off), dim, col0, t1);
+        load_cols<KT, VEC>(ctab + (row_off < last_off ? row_off : last_off), dim, ncol, t0);
+        load_cols<KT, VEC>(ctab + (row_off + dim < last_off ? row_off + dim : last_off), dim, ncol, t1);
 
         uint32_t kst = 1; // step 0 starts at the lane's root, already in `node`
         if (m != 0) {
@@ -839,7 +852,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 
             continue;
 #pragma unroll
         for (int t = 0; t < KT; t++) {
-            const uint32_t col = col0 + t;
+            const uint32_t col = col_of<KT, VEC>(ncol, t);
             if (col >= dim)
                 continue;
             uint32_t v = (uint32_t)tot[t][i];
