@@ -702,9 +702,11 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
 // gives a lane the shares of two consecutive rows, so the 64 lanes together
 // hold an [16 keys x 8 rows] share tile, exactly the A operand layout of
 // v_mfma_i32_16x16x32_i8 (lane l: row l mod 16, K slice (l / 16) * 8 .. +7),
-// and mfma_step() multiplies it into the table rows.
+// and mfma_step() multiplies it into the table rows: KT output tiles of 16
+// columns, for rows of up to 16 KT words (KT <= 8).  At KT = 8 a lane needs
+// more than 128 VGPRs, so one workgroup fits a CU instead of two.
 // ---------------------------------------------------------------------------
-constexpr int NW3 = 8;             // waves per workgroup (two workgroups per CU)
+constexpr int NW3 = 8;             // waves per workgroup (two workgroups per CU at KT <= 4)
 constexpr int HMAX3 = 9;           // largest per-lane subtree height of the wave kernel
 constexpr int NT3 = 64 * NW3;
 
