@@ -641,7 +641,7 @@ def batch_sweep(args):
     allk = torch.from_numpy(np.concatenate([K0, K1])).to(dev)  # key i pairs with key 512 + i
     want = W.table_rows_np(a, dim, seed)
     runs, ok = [], True
-    for B in (1, 2, 4, 8, 9, 12, 15, 16, 17, 24, 32, 64, 128, 256, 512, 1024):
+    for B in (1, 2, 4, 8, 9, 12, 15, 16, 17, 24, 32, 40, 64, 100, 128, 256, 512, 520, 1024):
         if B == 1:
             keys = allk[:1].contiguous()
         else:
@@ -656,7 +656,10 @@ def batch_sweep(args):
             rec = ((got[:half].astype(np.uint64) + got[half:2 * half]) & 0xFFFFFFFF).astype(np.uint32)
             ok &= bool((rec == want[:half]).all())
         plan = pir.plan(B, rows, dim, prf=args.prf)
-        runs.append({"keys": B, "kernel": "waves" if plan["kernel"] == pir.KERNEL_WAVES else "small_batch",
+        kern = "waves" if plan["kernel"] == pir.KERNEL_WAVES else "small_batch"
+        if plan["tail_keys"]:
+            kern += f" ({B - plan['tail_keys']} keys) + small_batch ({plan['tail_keys']} keys)"
+        runs.append({"keys": B, "kernel": kern,
                      "p50_ms": round(percentile(ms, 50), 4), "p99_ms": round(percentile(ms, 99), 4),
                      "server_qps": round(B / sec, 1)})
     return {"value": runs[-1]["server_qps"], "exact": ok, "batchsweep": runs,

@@ -220,6 +220,9 @@ typedef struct {
     uint64_t rows_per_item;
     uint32_t descent_levels;      /* tree levels walked from the root to an item's subtree */
     uint32_t bfs_levels;          /* breadth-first levels in LDS (small-batch kernel) */
+    uint32_t tail_keys;           /* the last tail_keys keys (1..8 past whole groups of 16) go to a
+                                     second launch on the small-batch kernel; the fields above
+                                     describe the first launch, over the other keys */
 } pir_plan_t;
 int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_plan_t *out);
 

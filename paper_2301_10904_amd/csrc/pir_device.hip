@@ -216,6 +216,25 @@ static bool use_wave_kernel(uint32_t prf_id, uint32_t n_keys, uint32_t n, uint32
     return n_keys >= wave_min_keys(prf_id, n, dim) && n >= 3 && dim <= 128;
 }
 
+// Keys of a batch that go to a launch of their own: a remainder of 1..8 keys
+// past whole groups of 16 runs on the small-batch kernel, where in the wave
+// kernel it would cost a whole group of items (and often a round of wave slots
+// of its own).  Measured with AES-128 (ChaCha20 alike): 17 keys on 2^20 rows
+// 0.81 -> 0.51 ms, 132 keys 4.42 -> 3.05 ms; 520 keys on 2^18 rows 4.46 ->
+// 2.95 ms; 17 keys on 2^22 rows 2.81 -> 1.87 ms.  Not below 2^17 rows (launch
+// bound), nor for 33..64 keys below 2^19 rows, where the wave launch fits one
+// round of slots and its partial group costs nothing (2^17: 0.25 -> 0.32 ms).
+// m is the log2 of the rows' aligned subtree.
+static uint32_t split_tail(uint32_t n_keys, uint32_t m)
+{
+    const uint32_t rem = n_keys % 16;
+    if (n_keys <= 16 || rem == 0 || rem > 8 || m < 17)
+        return 0;
+    if (m < 19 && n_keys > 32 && n_keys <= 64)
+        return 0;
+    return rem;
+}
+
 // Work plan of the small-batch kernel: Q keys per workgroup, chunks of 2^H
 // rows, breadth-first expansion to 2^lgS lanes per key, per-lane subtrees of
 // height H - lgS.  H is chosen so that the grid is about one round of
@@ -277,6 +296,15 @@ static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_str
     if (key_stride % 16 || key_stride < dpf_key_size(n) || ((uintptr_t)d_keys % 16) ||
         ((uintptr_t)d_table % 4) || ((uintptr_t)d_out % 4))
         return PIR_EINVAL;
+
+    if (const uint32_t tail = split_tail(n_keys, m)) {
+        const uint32_t head = n_keys - tail;
+        const int rc = answer_range<PRF>(d_keys, head, key_stride, n, row0, d_table, rows, dim, d_out, st);
+        if (rc != PIR_OK)
+            return rc;
+        return answer_range<PRF>(d_keys + (size_t)head * key_stride, tail, key_stride, n, row0, d_table, rows, dim,
+                                 d_out + (size_t)head * dim, st);
+    }
 
     if (use_wave_kernel(PRF::id, n_keys, m, dim)) {
         WaveTask t{};
@@ -449,6 +477,8 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
     const bool aes = prf_id == PIR_PRF_AES128;
     *out = pir_plan_t{};
     out->n = n;
+    out->tail_keys = split_tail(n_keys, n);
+    n_keys -= out->tail_keys; // the rest describes the first launch
     if (use_wave_kernel(prf_id, n_keys, n, dim)) {
         WaveTask t{};
         t.rows = rows;

@@ -47,7 +47,8 @@ class PirPlan(ctypes.Structure):
                 ("workgroups", ctypes.c_uint64), ("lanes_per_workgroup", ctypes.c_uint32),
                 ("lds_bytes", ctypes.c_uint32), ("keys_per_item", ctypes.c_uint32),
                 ("subtree_log", ctypes.c_uint32), ("rows_per_item", ctypes.c_uint64),
-                ("descent_levels", ctypes.c_uint32), ("bfs_levels", ctypes.c_uint32)]
+                ("descent_levels", ctypes.c_uint32), ("bfs_levels", ctypes.c_uint32),
+                ("tail_keys", ctypes.c_uint32)]
 
 
 class PirBins(ctypes.Structure):

@@ -601,3 +601,34 @@ def test_chacha20_wide_rows_above_2p20_on_waves(O, pirmod):
     assert (got[sample] == want).all()
     del T
     torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+@pytest.mark.parametrize("rows,dim,nkeys", [((1 << 17) - 3, 40, 20), ((1 << 18) + 1, 16, 37), (1 << 17, 8, 70)])
+def test_ragged_batches_split_off_the_remainder(O, pirmod, prf, rows, dim, nkeys):
+    """A remainder of 1..8 keys past whole groups of 16 is answered by a second
+    launch on the small-batch kernel (the first: the small-batch kernel for 16
+    keys, the wave kernel for 32 and 64): every per-server answer against the
+    oracle, both parties mixed."""
+    import torch
+
+    p = pirmod.plan(nkeys, rows, dim, prf=prf)
+    assert p["tail_keys"] == nkeys % 16 and p["tail_keys"] > 0
+    seed = rows + dim + 5 * nkeys + prf
+    n = log_domain(rows)
+    T = W.make_table(rows, dim, seed)
+    half = (nkeys + 1) // 2
+    alphas = W.uniform_indices(rows, half, seed)
+    alphas[0] = rows - 1
+    K0, K1 = O.gen_batch(n, alphas, W.key_seeds(half, seed), prf_id=prf)
+    keys = np.empty((2 * half, K0.shape[1]), np.uint8)
+    keys[0::2], keys[1::2] = K0, K1
+    keys = keys[:nkeys]
+    out = pirmod.answer(torch.from_numpy(keys).cuda(), T.cuda(), prf=prf)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    Tn = T.numpy().view(np.uint32)
+    want = O.answer_batch(keys, Tn, nthreads=cpu_threads())
+    assert (got == want).all()
+    for i in range(nkeys // 2):
+        assert (O.reconstruct(got[2 * i], got[2 * i + 1]) == Tn[alphas[i]]).all(), i

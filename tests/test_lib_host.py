@@ -265,8 +265,9 @@ def test_plan_small_wave_batches_fill_the_gpu():
     assert pir.plan(128, 1 << 20, 64)["subtree_log"] == 8
     for keys in (256, 1024, 4096):
         assert pir.plan(keys, 1 << 20, 64)["subtree_log"] == 9
-    for keys in (17, 31, 40, 100, 300, 5000):
+    for keys in (25, 31, 40, 100, 300, 5000):  # 40, 100 and 5000: the first launch, past the remainder
         p = pir.plan(keys, 1 << 20, 64)
+        assert p["kernel"] == pir.KERNEL_WAVES
         assert p["items"] >= 4096 and 3 <= p["subtree_log"] <= 9, (keys, p)
 
 
@@ -275,11 +276,11 @@ def test_plan_kernel_choice():
     assert pir.plan(1024, 1 << 20, 65)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(1024, 1 << 20, 128)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(16, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH     # AES-128, up to 2^20 rows: 16 keys
-    assert pir.plan(17, 1 << 20, 64)["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(25, 1 << 20, 64)["kernel"] == pir.KERNEL_WAVES           # 17..24: 16 + a remainder (below)
     assert pir.plan(8, (1 << 20) + 1, 64)["kernel"] == pir.KERNEL_SMALL_BATCH  # larger domains: 8 keys
     assert pir.plan(9, (1 << 20) + 1, 64)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(16, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH  # ChaCha20: 16
-    assert pir.plan(17, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(25, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
     # ChaCha20 on rows of 65..128 words above 2^20 rows: the wave kernel from 9 keys
     assert pir.plan(9, (1 << 20) + 1, 100, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(8, (1 << 20) + 1, 100, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH
@@ -292,6 +293,19 @@ def test_plan_kernel_choice():
     assert pir.plan(16, 1 << 20, 128)["keys_per_item"] == 8
     assert pir.plan(5, 1 << 20, 128)["keys_per_item"] == 8
     assert pir.plan(16, 1 << 20, 129)["keys_per_item"] == 16
+    # a remainder of 1..8 keys past whole groups of 16 runs as a second, small-batch launch
+    p = pir.plan(17, 1 << 20, 64)
+    assert p["tail_keys"] == 1 and p["kernel"] == pir.KERNEL_SMALL_BATCH and p["keys_per_item"] == 16
+    p = pir.plan(40, 1 << 20, 64)
+    assert p["tail_keys"] == 8 and p["kernel"] == pir.KERNEL_WAVES and p["items"] % 2 == 0
+    assert pir.plan(41, 1 << 20, 64)["tail_keys"] == 0      # a remainder of 9 fills its group well enough
+    assert pir.plan(32, 1 << 20, 64)["tail_keys"] == 0
+    assert pir.plan(16, 1 << 20, 64)["tail_keys"] == 0
+    assert pir.plan(20, 1 << 16, 64)["tail_keys"] == 0      # small domains stay one launch
+    assert pir.plan(20, 1 << 17, 64)["tail_keys"] == 4
+    assert pir.plan(40, 1 << 18, 64)["tail_keys"] == 0      # one round of wave slots anyway
+    assert pir.plan(40, (1 << 18) + 1, 64)["tail_keys"] == 8
+    assert pir.plan(70, 1 << 17, 64)["tail_keys"] == 6
     assert pir.plan(64, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH            # n = 2: too small for waves
     assert pir.plan(64, 8, 8)["kernel"] == pir.KERNEL_WAVES                  # n = 3
     rng = np.random.default_rng(5)
@@ -302,6 +316,13 @@ def test_plan_kernel_choice():
         p = pir.plan(keys, rows, dim)
         n = max(1, (rows - 1).bit_length())
         assert p["n"] == n
+        tail = p["tail_keys"]
+        if tail:  # a remainder past whole groups of 16 goes to a second launch
+            assert 1 <= tail <= 8 and keys > 16 and keys % 16 == tail and n >= 17
+            assert not (n < 19 and 32 < keys <= 64)
+        else:
+            assert keys <= 16 or keys % 16 == 0 or keys % 16 > 8 or n < 17 or (n < 19 and 32 < keys <= 64)
+        keys -= tail
         if p["kernel"] == pir.KERNEL_WAVES:
             assert keys >= (17 if n <= 20 else 9) and dim <= 128 and n >= 3
             assert p["descent_levels"] + p["subtree_log"] == n
