@@ -632,3 +632,30 @@ def test_ragged_batches_split_off_the_remainder(O, pirmod, prf, rows, dim, nkeys
     assert (got == want).all()
     for i in range(nkeys // 2):
         assert (O.reconstruct(got[2 * i], got[2 * i + 1]) == Tn[alphas[i]]).all(), i
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+def test_answer_multi_tails_on_large_tables(O, pirmod, prf):
+    """Tables of at least 2^20 rows send a remainder of 1..8 keys to a
+    small-batch launch of their own, the rest stays in the shared wave launch
+    (here: tails only, a group plus a tail, a group of exactly 16, and a
+    small table that keeps its partial group); every per-server answer
+    against the oracle."""
+    import torch
+
+    specs = [((1 << 20) + 3, 16, 5), (1 << 20, 8, 21), ((1 << 21) - 7, 4, 3), (1 << 20, 8, 16), (5000, 16, 7)]
+    tables, counts, keysets, expect = [], [], [], []
+    for i, (rows, dim, nk) in enumerate(specs):
+        seed = 90 + i + 10 * prf
+        T = W.make_table(rows, dim, seed)
+        tables.append(T.cuda())
+        counts.append(nk)
+        K, _ = O.gen_batch(log_domain(rows), W.uniform_indices(rows, nk, seed), W.key_seeds(nk, seed), prf_id=prf)
+        keysets.append(K)
+        expect.append(O.answer_batch(K, T.numpy().view(np.uint32), nthreads=cpu_threads()))
+    stride = (max(k.shape[1] for k in keysets) + 15) // 16 * 16
+    keys = np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keysets])
+    _, views = pirmod.answer_multi(tables, counts, torch.from_numpy(keys).cuda(), prf=prf)
+    torch.cuda.synchronize()
+    for t, (v, e) in enumerate(zip(views, expect)):
+        assert (v.cpu().numpy().view(np.uint32) == e).all(), t
