@@ -108,7 +108,8 @@ int dpf_gen_prf(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16
  * bad (version, party, n or PRF id) gets an all-zero output row and raises
  * the flag read by pir_check_status().  n_keys = 0 is a no-op returning PIR_OK.
  * Returns PIR_EINVAL on null pointers, bad sizes or misalignment (nothing is
- * launched), PIR_EHIP if a launch fails. */
+ * launched), PIR_ENOMEM if the call's work items reach 2^31 (tens of
+ * thousands of keys on a table of 2^32 rows), PIR_EHIP if a launch fails. */
 int pir_answer(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride,
                const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out,
                void *stream);

@@ -387,8 +387,15 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
             return PIR_EINVAL;
     }
     // tables the wave kernel takes go out grouped by column class, up to
-    // MAX_TASKS per launch; the rest one by one
+    // MAX_TASKS per launch; the rest one by one, and the remainders split off
+    // large tables after the wave launches
     std::vector<WaveTask> cls[7];
+    struct Tail {
+        uint32_t table, n_keys; // the last n_keys keys of table `table`, at keys, answered into out
+        const uint8_t *keys;
+        uint32_t *out;
+    };
+    std::vector<Tail> tails;
     size_t key_off = 0, out_off = 0;
     for (uint32_t t = 0; t < n_tables; t++) {
         const pir_table_t &T = tables[t];
@@ -415,12 +422,8 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
                 w.n_bins = 1;
                 cls[c].push_back(w);
             }
-            if (tail) {
-                int st = answer_one<PRF>(kp + (size_t)head * key_stride, tail, key_stride, T.d_table, T.rows, T.dim,
-                                         op + (size_t)head * T.dim, (hipStream_t)stream);
-                if (st != PIR_OK)
-                    return st;
-            }
+            if (tail)
+                tails.push_back({t, tail, kp + (size_t)head * key_stride, op + (size_t)head * T.dim});
         } else {
             int st = answer_one<PRF>(kp, T.n_keys, key_stride, T.d_table, T.rows, T.dim, op, (hipStream_t)stream);
             if (st != PIR_OK)
@@ -434,6 +437,12 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
             if (st != PIR_OK)
                 return st;
         }
+    for (const Tail &r : tails) {
+        const pir_table_t &T = tables[r.table];
+        int st = answer_one<PRF>(r.keys, r.n_keys, key_stride, T.d_table, T.rows, T.dim, r.out, (hipStream_t)stream);
+        if (st != PIR_OK)
+            return st;
+    }
     return PIR_OK;
 }
 

@@ -385,3 +385,18 @@ def test_peak_probes_export_and_reject_bad_arguments():
     assert f(0, 1, 1, buf, 0, out, None) == -1                        # empty input
     assert f(0, 1, 1, buf, 1022, out, None) == -1                     # not whole 16-byte units
     assert f(0, 1, 1, ctypes.c_void_p(0x1004), 1024, out, None) == -1  # misaligned input
+
+
+def test_too_much_work_is_refused_before_any_launch(lib):
+    """16384 keys on a table of 2^32 rows would need 2^31 wave items: the plan
+    and the call both return PIR_ENOMEM, and the call touches no device
+    memory (placeholder pointers, no GPU here)."""
+    import ctypes
+
+    out = pir.PirPlan()
+    assert lib.pir_plan(0, 16384, 1 << 32, 1, ctypes.byref(out)) == pir.PIR_ENOMEM
+    assert lib.pir_plan(0, 16368, 1 << 32, 1, ctypes.byref(out)) == pir.PIR_OK  # 1023 groups of 16
+    stride = (pir.key_size(32) + 15) // 16 * 16
+    fake = ctypes.c_void_p(0x100000)
+    assert lib.pir_answer(fake, 16384, stride, fake, 1 << 32, 1, fake, None) == pir.PIR_ENOMEM
+    assert lib.pir_answer_prf(1, fake, 16384, stride, fake, 1 << 32, 1, fake, None) == pir.PIR_ENOMEM
