@@ -187,29 +187,41 @@ static int wave_class(uint32_t dim)
 }
 
 // Which kernel answers one table: the wave kernel (int8 matrix cores, up to 16
-// keys per wave) from a batch size on that depends on the PRF and the domain,
-// else the small-batch kernel, which also takes rows wider than 128 words.
-// Every lane of the wave kernel walks its own path from the root, while the
-// small-batch kernel shares the path above its chunks; for small domains that
-// repeated descent outweighs everything else.  Measured (p50 per call, rows of
-// 64 words): 9..16 keys on 2^20 rows take 0.42 ms on the small-batch kernel
-// against 0.59 on the wave kernel with AES-128, 0.46 against 1.02 with
-// ChaCha20; on 2^22 rows 1.60 against 1.56 ms with AES-128.  From 17 keys the
-// wave kernel is as fast or faster with AES-128 (0.81 against 0.82 ms at 17,
-// 1.45 against 1.61 at 64 keys on 2^20 rows).  With ChaCha20 the small-batch
-// kernel would still win at 19..64 keys on 2^20 rows (0.91 against 1.03 ms at
-// 32), but a second group holding only 1 or 2 keys runs 26% longer than one
-// with more, for a reason not found, so ChaCha20 also hands over at 17.
-// Rows of 65..128 words: the small-batch kernel holds two column chunks and
-// at most 8 keys per workgroup (plan_fused); with ChaCha20 on 2^22 rows 9..16
-// keys then take 3.6 ms there against 2.2-2.4 ms on the wave kernel, so above
-// 2^20 rows ChaCha20 hands over at 9 keys for such rows as AES-128 does for
-// all (at 2^20 the small-batch kernel still wins: 0.92 against 0.98-1.03 ms).
+// keys per wave) from a batch size on that depends on the PRF, the domain and
+// the row width, else the small-batch kernel, which also takes rows wider than
+// 128 words.  Every lane of the wave kernel walks its own path from the root,
+// while the small-batch kernel shares the path above its chunks; for small
+// domains that repeated descent outweighs everything else.  Measured (p50 per
+// call, rows of 64 words): 9..16 keys on 2^20 rows take 0.42 ms on the
+// small-batch kernel against 0.59 on the wave kernel with AES-128, 0.46
+// against 1.02 with ChaCha20.
+// On domains up to 2^20 with rows of at most 64 words the small-batch kernel,
+// whose workgroups share the path above their chunk, stays ahead until the
+// batch is large enough for the wave kernel's matrix-core product to pay:
+// from 32 2^(20-n) keys with AES-128 and 256 2^(20-n) with ChaCha20.
+// Measured (1 table x 64 words, one build against the other): AES-128 on
+// 2^14 rows 25 keys 0.042 against 0.101 ms, 1024 keys 0.411 against 0.432;
+// on 2^18 rows 64 keys 0.417 against 0.428, 128 keys 0.809 against 0.776; on
+// 2^20 rows 25 keys 0.806 against 0.817, 48 keys 1.196 against 1.127.
+// ChaCha20 on 2^20 rows 128 keys 3.58 against 3.65 ms, 256 keys 7.15 against
+// 7.09; on 2^14 rows 25 keys 0.033 against 0.112.  (Remainders of 1..8 keys
+// past whole groups of 16 run as launches of their own, split_tail.)  Above
+// 2^20 rows the wave kernel takes AES-128 batches from 9 keys and ChaCha20
+// ones from 17: 9..16 keys on 2^22 rows take 1.56 against 1.60 ms with
+// AES-128.  Rows of 65..128 words (two column chunks): the small-batch
+// kernel holds at most 8 keys per workgroup (plan_fused), and the wave kernel
+// takes batches from 17 keys, above 2^20 rows from 9 (ChaCha20 on 2^22 rows:
+// 9..16 keys 3.6 ms there against 2.2-2.4 ms on the wave kernel).
 static uint32_t wave_min_keys(uint32_t prf_id, uint32_t n, uint32_t dim)
 {
-    if (prf_id == PIR_PRF_CHACHA20)
-        return n > 20 && dim > 64 ? 9u : 17u;
-    return n <= 20 ? 17u : 9u;
+    const bool chacha = prf_id == PIR_PRF_CHACHA20;
+    if (dim > 64)
+        return n > 20 ? 9u : 17u;
+    if (n > 20)
+        return chacha ? 17u : 9u;
+    const uint32_t shift = 20 - n;
+    const uint32_t base = chacha ? 256u : 32u; // 2^8 and 2^5
+    return shift + (chacha ? 8u : 5u) >= 32 ? 0xffffffffu : base << shift;
 }
 static bool use_wave_kernel(uint32_t prf_id, uint32_t n_keys, uint32_t n, uint32_t dim)
 {

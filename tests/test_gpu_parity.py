@@ -604,16 +604,18 @@ def test_chacha20_wide_rows_above_2p20_on_waves(O, pirmod):
 
 
 @pytest.mark.parametrize("prf", [0, 1])
-@pytest.mark.parametrize("rows,dim,nkeys", [((1 << 17) - 3, 40, 20), ((1 << 18) + 1, 16, 37), (1 << 17, 8, 70)])
+@pytest.mark.parametrize("rows,dim,nkeys", [((1 << 17) - 3, 40, 20), ((1 << 18) + 1, 16, 37), (1 << 17, 8, 70),
+                                            ((1 << 19) + 3, 8, 264)])
 def test_ragged_batches_split_off_the_remainder(O, pirmod, prf, rows, dim, nkeys):
     """A remainder of 1..8 keys past whole groups of 16 is answered by a second
-    launch on the small-batch kernel (the first: the small-batch kernel for 16
-    keys, the wave kernel for 32 and 64): every per-server answer against the
-    oracle, both parties mixed."""
+    launch on the small-batch kernel (the first: the small-batch kernel, or
+    for 256 keys on 2^20 rows' domain the wave kernel): every per-server
+    answer against the oracle, both parties mixed."""
     import torch
 
     p = pirmod.plan(nkeys, rows, dim, prf=prf)
     assert p["tail_keys"] == nkeys % 16 and p["tail_keys"] > 0
+    assert (p["kernel"] == pirmod.KERNEL_WAVES) == (nkeys == 264)
     seed = rows + dim + 5 * nkeys + prf
     n = log_domain(rows)
     T = W.make_table(rows, dim, seed)

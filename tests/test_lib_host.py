@@ -265,7 +265,7 @@ def test_plan_small_wave_batches_fill_the_gpu():
     assert pir.plan(128, 1 << 20, 64)["subtree_log"] == 8
     for keys in (256, 1024, 4096):
         assert pir.plan(keys, 1 << 20, 64)["subtree_log"] == 9
-    for keys in (25, 31, 40, 100, 300, 5000):  # 40, 100 and 5000: the first launch, past the remainder
+    for keys in (33, 40, 47, 100, 300, 5000):  # 33, 40, 100 and 5000: the first launch, past the remainder
         p = pir.plan(keys, 1 << 20, 64)
         assert p["kernel"] == pir.KERNEL_WAVES
         assert p["items"] >= 4096 and 3 <= p["subtree_log"] <= 9, (keys, p)
@@ -276,11 +276,20 @@ def test_plan_kernel_choice():
     assert pir.plan(1024, 1 << 20, 65)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(1024, 1 << 20, 128)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(16, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH     # AES-128, up to 2^20 rows: 16 keys
-    assert pir.plan(25, 1 << 20, 64)["kernel"] == pir.KERNEL_WAVES           # 17..24: 16 + a remainder (below)
+    assert pir.plan(31, 1 << 20, 64)["kernel"] == pir.KERNEL_SMALL_BATCH     # AES-128 on 2^20 rows: up to 31 keys
+    assert pir.plan(32, 1 << 20, 64)["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(127, 1 << 18, 64)["kernel"] == pir.KERNEL_SMALL_BATCH    # 2^18 rows: up to 127
+    assert pir.plan(128, 1 << 18, 64)["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(2047, 1 << 14, 64)["kernel"] == pir.KERNEL_SMALL_BATCH   # 2^14 rows: up to 2047
+    assert pir.plan(2048, 1 << 14, 64)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(8, (1 << 20) + 1, 64)["kernel"] == pir.KERNEL_SMALL_BATCH  # larger domains: 8 keys
     assert pir.plan(9, (1 << 20) + 1, 64)["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(16, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH  # ChaCha20: 16
-    assert pir.plan(25, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(255, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH  # up to 255 on 2^20
+    assert pir.plan(256, 1 << 20, 64, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(1024, 1 << 17, 64, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH
+    assert pir.plan(25, (1 << 20) + 1, 64, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(25, 1 << 20, 100, prf="chacha20")["kernel"] == pir.KERNEL_WAVES  # wider rows: from 17
     # ChaCha20 on rows of 65..128 words above 2^20 rows: the wave kernel from 9 keys
     assert pir.plan(9, (1 << 20) + 1, 100, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
     assert pir.plan(8, (1 << 20) + 1, 100, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH
@@ -306,8 +315,9 @@ def test_plan_kernel_choice():
     assert pir.plan(40, 1 << 18, 64)["tail_keys"] == 0      # one round of wave slots anyway
     assert pir.plan(40, (1 << 18) + 1, 64)["tail_keys"] == 8
     assert pir.plan(70, 1 << 17, 64)["tail_keys"] == 6
-    assert pir.plan(64, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH            # n = 2: too small for waves
-    assert pir.plan(64, 8, 8)["kernel"] == pir.KERNEL_WAVES                  # n = 3
+    assert pir.plan(1 << 22, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH       # n = 2: too small for waves
+    assert pir.plan(1 << 22, 8, 8)["kernel"] == pir.KERNEL_WAVES             # n = 3: from 32 * 2^17 keys
+    assert pir.plan(17, 8, 100)["kernel"] == pir.KERNEL_WAVES                # wider rows: from 17 keys
     rng = np.random.default_rng(5)
     for _ in range(300):
         keys = int(rng.integers(1, 5000))
@@ -323,8 +333,12 @@ def test_plan_kernel_choice():
         else:
             assert keys <= 16 or keys % 16 == 0 or keys % 16 > 8 or n < 17 or (n < 19 and 32 < keys <= 64)
         keys -= tail
+        if dim > 64:
+            wave_min = 9 if n > 20 else 17
+        else:
+            wave_min = 9 if n > 20 else 32 << (20 - n)
+        assert (p["kernel"] == pir.KERNEL_WAVES) == (keys >= wave_min and dim <= 128 and n >= 3), (keys, rows, dim)
         if p["kernel"] == pir.KERNEL_WAVES:
-            assert keys >= (17 if n <= 20 else 9) and dim <= 128 and n >= 3
             assert p["descent_levels"] + p["subtree_log"] == n
             chunks = -(-rows // p["rows_per_item"])
             assert p["items"] == chunks * -(-keys // 16)
