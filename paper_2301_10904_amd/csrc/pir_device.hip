@@ -210,13 +210,21 @@ static int wave_class(uint32_t dim)
 // ones from 17: 9..16 keys on 2^22 rows take 1.56 against 1.60 ms with
 // AES-128.  Rows of 65..128 words (two column chunks): the small-batch
 // kernel holds at most 8 keys per workgroup (plan_fused), and the wave kernel
-// takes batches from 17 keys, above 2^20 rows from 9 (ChaCha20 on 2^22 rows:
-// 9..16 keys 3.6 ms there against 2.2-2.4 ms on the wave kernel).
+// takes batches from 17 keys on 2^17..2^20 rows, above 2^20 rows from 9
+// (ChaCha20 on 2^22 rows: 9..16 keys 3.6 ms there against 2.2-2.4 ms on the
+// wave kernel), and on smaller domains from 64 2^(16-n) keys with AES-128 and
+// 128 2^(16-n) with ChaCha20 (2^14 x 128: 25 keys 0.048 against 0.068 ms
+// with AES-128, 0.038 against 0.081 with ChaCha20; 512 keys 0.317 against
+// 0.283 and 0.343 against 0.307; 2^18 x 128, 25 keys: 0.357 against 0.295).
 static uint32_t wave_min_keys(uint32_t prf_id, uint32_t n, uint32_t dim)
 {
     const bool chacha = prf_id == PIR_PRF_CHACHA20;
-    if (dim > 64)
-        return n > 20 ? 9u : 17u;
+    if (dim > 64) {
+        if (n > 16)
+            return n > 20 ? 9u : 17u;
+        const uint32_t shift = 16 - n; // at most 15
+        return (chacha ? 128u : 64u) << shift;
+    }
     if (n > 20)
         return chacha ? 17u : 9u;
     const uint32_t shift = 20 - n;

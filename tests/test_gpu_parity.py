@@ -498,8 +498,9 @@ def test_single_key_streamed_wide_rows(O, pirmod, prf, dim):
 
 WIDE_WAVE_CASES = [
     # rows, dim, keys: rows of 65..128 words on the wave kernel (eight column
-    # tiles), one and several key groups, ragged row counts and key groups
-    (1 << 12, 65, 40), (3001, 100, 18), ((1 << 14) + 5, 128, 33), ((1 << 13) - 1, 127, 17),
+    # tiles), several key groups, ragged row counts and key groups
+    ((1 << 16) + 3, 65, 41), ((1 << 17) - 1, 100, 25), ((1 << 17) + 5, 128, 48), ((1 << 16) + 9, 127, 32),
+    ((1 << 14) - 3, 100, 528),
 ]
 
 

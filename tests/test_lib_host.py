@@ -317,7 +317,11 @@ def test_plan_kernel_choice():
     assert pir.plan(70, 1 << 17, 64)["tail_keys"] == 6
     assert pir.plan(1 << 22, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH       # n = 2: too small for waves
     assert pir.plan(1 << 22, 8, 8)["kernel"] == pir.KERNEL_WAVES             # n = 3: from 32 * 2^17 keys
-    assert pir.plan(17, 8, 100)["kernel"] == pir.KERNEL_WAVES                # wider rows: from 17 keys
+    assert pir.plan(25, 1 << 17, 100)["kernel"] == pir.KERNEL_WAVES          # wider rows: from 17 keys
+    assert pir.plan(255, 1 << 14, 100)["kernel"] == pir.KERNEL_SMALL_BATCH   # small domains: from 64 2^(16-n)
+    assert pir.plan(256, 1 << 14, 100)["kernel"] == pir.KERNEL_WAVES
+    assert pir.plan(511, 1 << 14, 100, prf="chacha20")["kernel"] == pir.KERNEL_SMALL_BATCH
+    assert pir.plan(512, 1 << 14, 100, prf="chacha20")["kernel"] == pir.KERNEL_WAVES
     rng = np.random.default_rng(5)
     for _ in range(300):
         keys = int(rng.integers(1, 5000))
@@ -334,7 +338,7 @@ def test_plan_kernel_choice():
             assert keys <= 16 or keys % 16 == 0 or keys % 16 > 8 or n < 17 or (n < 19 and 32 < keys <= 64)
         keys -= tail
         if dim > 64:
-            wave_min = 9 if n > 20 else 17
+            wave_min = 9 if n > 20 else 17 if n > 16 else 64 << (16 - n)
         else:
             wave_min = 9 if n > 20 else 32 << (20 - n)
         assert (p["kernel"] == pir.KERNEL_WAVES) == (keys >= wave_min and dim <= 128 and n >= 3), (keys, rows, dim)
