@@ -242,15 +242,17 @@ static bool use_wave_kernel(uint32_t prf_id, uint32_t n_keys, uint32_t n, uint32
 // of its own).  Measured with AES-128 (ChaCha20 alike): 17 keys on 2^20 rows
 // 0.81 -> 0.51 ms, 132 keys 4.42 -> 3.05 ms; 520 keys on 2^18 rows 4.46 ->
 // 2.95 ms; 17 keys on 2^22 rows 2.81 -> 1.87 ms.  Not below 2^17 rows (launch
-// bound), nor for 33..64 keys below 2^19 rows, where the wave launch fits one
-// round of slots and its partial group costs nothing (2^17: 0.25 -> 0.32 ms).
-// m is the log2 of the rows' aligned subtree.
+// bound).  On 2^17 and 2^18 rows a batch of at most 64 keys splits off only a
+// remainder of up to 4 keys: 33 keys on 2^18 rows 0.324 -> 0.264 ms (AES-128),
+// 49 keys 0.585 -> 0.387 ms (ChaCha20), but 56 keys 0.221 -> 0.245 ms and 24
+// keys 0.123 -> 0.140 ms on 2^17 rows with a remainder of 8.  m is the log2
+// of the rows' aligned subtree.
 static uint32_t split_tail(uint32_t n_keys, uint32_t m)
 {
     const uint32_t rem = n_keys % 16;
     if (n_keys <= 16 || rem == 0 || rem > 8 || m < 17)
         return 0;
-    if (m < 19 && n_keys > 32 && n_keys <= 64)
+    if (m < 19 && n_keys <= 64 && rem > 4)
         return 0;
     return rem;
 }

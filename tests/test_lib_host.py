@@ -312,7 +312,9 @@ def test_plan_kernel_choice():
     assert pir.plan(16, 1 << 20, 64)["tail_keys"] == 0
     assert pir.plan(20, 1 << 16, 64)["tail_keys"] == 0      # small domains stay one launch
     assert pir.plan(20, 1 << 17, 64)["tail_keys"] == 4
-    assert pir.plan(40, 1 << 18, 64)["tail_keys"] == 0      # one round of wave slots anyway
+    assert pir.plan(40, 1 << 18, 64)["tail_keys"] == 0      # up to 64 keys below 2^19 rows: remainders of 1..4
+    assert pir.plan(36, 1 << 18, 64)["tail_keys"] == 4
+    assert pir.plan(24, 1 << 17, 64)["tail_keys"] == 0
     assert pir.plan(40, (1 << 18) + 1, 64)["tail_keys"] == 8
     assert pir.plan(70, 1 << 17, 64)["tail_keys"] == 6
     assert pir.plan(1 << 22, 4, 8)["kernel"] == pir.KERNEL_SMALL_BATCH       # n = 2: too small for waves
@@ -333,9 +335,9 @@ def test_plan_kernel_choice():
         tail = p["tail_keys"]
         if tail:  # a remainder past whole groups of 16 goes to a second launch
             assert 1 <= tail <= 8 and keys > 16 and keys % 16 == tail and n >= 17
-            assert not (n < 19 and 32 < keys <= 64)
+            assert not (n < 19 and keys <= 64 and tail > 4)
         else:
-            assert keys <= 16 or keys % 16 == 0 or keys % 16 > 8 or n < 17 or (n < 19 and 32 < keys <= 64)
+            assert keys <= 16 or keys % 16 == 0 or keys % 16 > 8 or n < 17 or (n < 19 and keys <= 64 and keys % 16 > 4)
         keys -= tail
         if dim > 64:
             wave_min = 9 if n > 20 else 17 if n > 16 else 64 << (16 - n)
