@@ -167,7 +167,9 @@ def main():
     ap.add_argument("--log-rows", type=int, default=20)
     ap.add_argument("--dim", type=int, default=64)
     ap.add_argument("--seed", type=int, default=2)
-    ap.add_argument("--single-steps", type=int, default=50)
+    ap.add_argument("--single-steps", type=int, default=200)
+    ap.add_argument("--latency-samples", type=int, default=100,
+                    help="batched launches timed after the timed region, for the p50/p99 latency")
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="keys of the workload the oracle answers for the CPU baseline (x8 for ChaCha20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -258,6 +260,17 @@ def main():
     recon_ok = bool(all((pir.reconstruct(got[p], got[pairs + p]) == want[p]).all()
                         for p in range(pairs)))
 
+    # the latency distribution: the timed launches and --latency-samples more
+    # (value, ms_per_step and the roofline use the timed region alone)
+    lev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(args.latency_samples)]
+    for e0, e1 in lev:
+        e0.record()
+        pir.answer(keys, table, out, prf=prf)
+        e1.record()
+    torch.cuda.synchronize()
+    lat_ms = launch_ms + [e0.elapsed_time(e1) for e0, e1 in lev]
+
     # the unbatched single-query kernel on the same table
     k1 = keys[:1].contiguous()
     o1 = torch.empty((1, dim), dtype=torch.int32, device=dev)
@@ -338,11 +351,11 @@ def main():
                                f"{'AES-128' if prf == 'aes128' else 'ChaCha20'} PRF",
                    "rows": rows, "dim": dim, "keys_per_step": B, "log_domain": n, "prf": prf},
         "retrieval_qps": round(value / 2, 2),
-        "batched_latency_ms": {"p50": round(percentile(launch_ms, 50), 4),
-                               "p99": round(percentile(launch_ms, 99), 4)},
+        "batched_latency_ms": {"p50": round(percentile(lat_ms, 50), 4),
+                               "p99": round(percentile(lat_ms, 99), 4), "samples": len(lat_ms)},
         "single_query": {"qps": round(args.single_steps / (s1 - s0), 2),
                          "p50_ms": round(percentile(single_ms, 50), 4),
-                         "p99_ms": round(percentile(single_ms, 99), 4)},
+                         "p99_ms": round(percentile(single_ms, 99), 4), "samples": args.single_steps},
         "exact": recon_ok,
         "roofline": roofline,
         "roofline_lds": roofline_lds,
