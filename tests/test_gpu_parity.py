@@ -663,3 +663,51 @@ def test_answer_multi_tails_on_large_tables(O, pirmod, prf):
     torch.cuda.synchronize()
     for t, (v, e) in enumerate(zip(views, expect)):
         assert (v.cpu().numpy().view(np.uint32) == e).all(), t
+
+
+def random_cases(rng):
+    """(rows, dim, keys, prf): random small cases; narrow rows at and above the
+    wave kernel's batch threshold (AES-128 on 2^14..2^18 rows, ChaCha20 just
+    above 2^20 rows); rows of 65..128 words on 2^17..2^18 rows."""
+    cases = []
+    for _ in range(20):
+        n = int(rng.integers(1, 20))
+        rows = int(rng.integers((1 << (n - 1)) + 1, (1 << n) + 1)) if n > 1 else int(rng.integers(1, 3))
+        dim = int(rng.choice([1, 3, 16, 33, 64, 65, 100, 128, 130]))
+        cap = max(1, min(600, (1 << 22) // rows, (1 << 26) // (rows * dim)))
+        cases.append((rows, dim, int(rng.integers(1, cap + 1)), int(rng.integers(0, 2))))
+    for _ in range(4):
+        n = int(rng.choice([14, 16, 18]))
+        rows = int(rng.integers((1 << (n - 1)) + 1, (1 << n) + 1))
+        cases.append((rows, int(rng.choice([8, 16])), (32 << (20 - n)) + int(rng.integers(0, 24)), 0))
+    for _ in range(2):
+        rows = int(rng.integers((1 << 20) + 1, (1 << 20) + 5000))
+        cases.append((rows, 8, int(rng.integers(17, 40)), 1))
+    for _ in range(4):
+        n = int(rng.choice([17, 18]))
+        rows = int(rng.integers((1 << (n - 1)) + 1, (1 << n) + 1))
+        cases.append((rows, int(rng.choice([65, 100, 128])), int(rng.integers(17, 41)), int(rng.integers(0, 2))))
+    return cases
+
+
+def test_random_shapes_against_the_oracle(O, pirmod):
+    """A seeded sweep over table sizes, row widths, batch sizes and both PRFs,
+    bounded so the oracle answers each case in about a second at most; it
+    reaches both kernels and the split-off remainder.  Every per-server answer
+    against the oracle."""
+    import torch
+
+    seen = set()
+    for case, (rows, dim, nkeys, prf) in enumerate(random_cases(np.random.default_rng(2301))):
+        p = pirmod.plan(nkeys, rows, dim, prf=prf)
+        seen.add((p["kernel"], p["tail_keys"] > 0))
+        seed = 7000 + case
+        T = W.make_table(rows, dim, seed)
+        alphas = W.uniform_indices(rows, nkeys, seed)
+        K, _ = O.gen_batch(log_domain(rows), alphas, W.key_seeds(nkeys, seed), prf_id=prf)
+        out = pirmod.answer(torch.from_numpy(K).cuda(), T.cuda(), prf=prf)
+        torch.cuda.synchronize()
+        want = O.answer_batch(K, T.numpy().view(np.uint32), nthreads=cpu_threads())
+        assert (out.cpu().numpy().view(np.uint32) == want).all(), (case, rows, dim, nkeys, prf, p)
+    assert {(pirmod.KERNEL_WAVES, False), (pirmod.KERNEL_SMALL_BATCH, False)} <= seen, seen
+    assert any(tail for _, tail in seen), seen
