@@ -192,14 +192,18 @@ def main():
                     help="the DPF tree's PRF (section 3.2.6): AES-128 (default) or ChaCha20")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="summarise rocprofv3 --pmc counter CSVs of this benchmark and exit")
+    ap.add_argument("--pmc-kernel", default="k_pir_waves",
+                    help="with --pmc-summary: the kernel whose dispatches are summarised (a name substring)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (read + write) three times, "
                          "to scale HBM traffic counters")
     args = ap.parse_args()
 
     if args.pmc_summary:
-        avg, scale, dispatches = pmc_summary(args.pmc_summary, copy_mib=args.calibrate_copy or 256)
-        out = {"kernel": f"k_pir_waves (the 1024-key launch, {args.prf})", "prf": args.prf,
+        avg, scale, dispatches = pmc_summary(args.pmc_summary, kernel_substr=args.pmc_kernel,
+                                             copy_mib=args.calibrate_copy or 256)
+        what = "the 1024-key launch" if args.pmc_kernel == "k_pir_waves" else "dispatches matching the name"
+        out = {"kernel": f"{args.pmc_kernel} ({what}, {args.prf})", "prf": args.prf,
                "dispatches": dispatches, "counters_avg": avg,
                "copy_scale": scale, "kernel_digest": kernel_digest()}
         if "FETCH_SIZE" in avg and "WRITE_SIZE" in avg and len(scale) == 2:
@@ -288,14 +292,7 @@ def main():
     s1 = time.perf_counter()
     single_ms = [e0.elapsed_time(e1) for e0, e1 in sev]
 
-    if args.calibrate_copy:
-        src = torch.empty(args.calibrate_copy << 18, dtype=torch.int32, device=dev).fill_(1)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
+    calibration_copy(args.calibrate_copy, dev)
 
     valu_ops, lookups = algorithmic_work(n, B, dim, prf=prf)
     kern_s = float(np.mean(launch_ms)) / 1e3
@@ -492,6 +489,22 @@ def time_launches(fn, steps, warmup):
     return (time.perf_counter() - t0) / steps, [a.elapsed_time(b) for a, b in evs]
 
 
+def calibration_copy(mib: int, dev) -> None:
+    """A plain device copy of `mib` MiB, three times: what the HBM traffic
+    counters read for it scales their readings of the PIR kernels."""
+    if not mib:
+        return
+    import torch
+
+    src = torch.empty(mib << 18, dtype=torch.int32, device=dev).fill_(1)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    del src, dst
+
+
 def other_modes(args):
     """The other workloads: one JSON line each (not the driver's default line)."""
     import torch
@@ -564,6 +577,7 @@ def other_modes(args):
         gbs = rows * dim * 4 / (p50 * 1e-3) / 1e9
         del T
         torch.cuda.empty_cache()
+        calibration_copy(args.calibrate_copy, dev)
         peaks = measured_peaks() if args.peaks else None
         hbm = {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                "frac": round(gbs / HBM_PEAK_GBS, 4), "bytes": rows * dim * 4}

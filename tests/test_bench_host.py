@@ -102,3 +102,25 @@ def test_pmc_summary_averages_dispatches_and_scales_by_the_copy(tmp_path):
     out = json.loads(r.stdout)
     assert out["bytes_per_launch"] == 1024 * (200 * 2 + 2000 * 1)
     assert out["kernel_digest"] == bench.kernel_digest()
+
+
+def test_pmc_summary_of_another_kernel(tmp_path):
+    """--pmc-kernel selects the dispatches summarised: here the single-key
+    kernel's, ignoring the batched kernel's in the same file."""
+    fused = "void (anonymous namespace)::k_pir_fused<AesPrf, 1, 1, true, true>(FusedArgs)"
+    waves = "void (anonymous namespace)::k_pir_waves<AesPrf, 4, true>(WaveTasks, unsigned int)"
+    copy = "__amd_rocclr_copyBuffer"
+    fetch = tmp_path / "fetch.csv"
+    write_pmc(fetch, [(1, waves, "FETCH_SIZE", 900.0), (2, fused, "FETCH_SIZE", 50.0),
+                      (3, fused, "FETCH_SIZE", 70.0), (4, copy, "FETCH_SIZE", 131072.0)])
+    write = tmp_path / "write.csv"
+    write_pmc(write, [(1, waves, "WRITE_SIZE", 900.0), (2, fused, "WRITE_SIZE", 4.0),
+                      (4, copy, "WRITE_SIZE", 262144.0)])
+    r = subprocess.run([sys.executable, str(ROOT / "bench.py"), "--pmc-summary", str(fetch), str(write),
+                        "--pmc-kernel", "k_pir_fused", "--calibrate-copy", "256"],
+                       capture_output=True, text=True, cwd=ROOT, timeout=120)
+    assert r.returncode == 0, r.stderr
+    out = json.loads(r.stdout)
+    assert out["kernel"].startswith("k_pir_fused")
+    assert out["counters_avg"] == {"FETCH_SIZE": 60.0, "WRITE_SIZE": 4.0}
+    assert out["bytes_per_launch"] == 1024 * (60 * 2 + 4 * 1)
