@@ -400,6 +400,7 @@ PEAK_PROBES = {
 PEAK_NAMES = {"valu": "valu_T_lane_ops", "lds": "lds_T_lookups", "mfma_i8": "mfma_i8_TOPs",
               "mfma_i8_k32": "mfma_i8_16x16x32_TOPs"}
 HBM_PROBE_WORDS = 1 << 30
+HBM_PROBE_BLOCKS = (256, 512, 1024)
 
 
 def measured_peaks() -> dict | None:
@@ -425,9 +426,13 @@ def measured_peaks() -> dict | None:
         if rc != 0:
             raise RuntimeError(f"pir_peak_probe({kind}) failed: {rc}")
 
-    _, ms = time_launches(lambda: probe(0, 2048, 0, buf), 5, 1)
-    res["hbm_read_GBs"] = round(HBM_PROBE_WORDS * 4 / (float(np.median(ms)) * 1e-3) / 1e9, 1)
-    ok = int(out[:2048 * 256].to(torch.int64).sum().item()) % (1 << 32) == (3 * HBM_PROBE_WORDS) % (1 << 32)
+    # the best of three grid sizes: one, two and four workgroups per CU
+    ok, best = True, 0.0
+    for blocks in HBM_PROBE_BLOCKS:
+        _, ms = time_launches(lambda: probe(0, blocks, 0, buf), 5, 1)
+        best = max(best, HBM_PROBE_WORDS * 4 / (float(np.median(ms)) * 1e-3) / 1e9)
+        ok &= int(out[:blocks * 256].to(torch.int64).sum().item()) % (1 << 32) == (3 * HBM_PROBE_WORDS) % (1 << 32)
+    res["hbm_read_GBs"] = round(best, 1)
     del buf
     for name, (kind, blocks, iters, lanes, per_lane) in PEAK_PROBES.items():
         _, ms = time_launches(lambda: probe(kind, blocks, iters), 5, 1)
@@ -436,7 +441,8 @@ def measured_peaks() -> dict | None:
     res["published"] = {"hbm_read_GBs": HBM_PEAK_GBS, "valu_T_lane_ops": round(PEAK_INT32_OPS / 1e12, 3),
                         "lds_T_lookups": round(PEAK_LDS_LOOKUPS / 1e12, 3), "mfma_i8_TOPs": 5000.0}
     res["hbm_checksum_ok"] = ok
-    res["probes"] = ("pir_peak_probe: 4 GiB non-temporal 16-byte reads; 16 v_xor_b32 chains per lane; "
+    res["probes"] = ("pir_peak_probe: 4 GiB of non-temporal 16-byte reads, a contiguous share per workgroup, "
+                     "16 loads in flight per lane, best of 256/512/1024 workgroups; 16 v_xor_b32 chains per lane; "
                      "8 ds_read_b32 chains per lane in the AES table layout (64 KiB, 1024 lanes, 2 per CU); "
                      "8 v_mfma_i32_16x16x64_i8 (and, separately, 16x16x32) accumulators per wave")
     return res

@@ -2,8 +2,11 @@
 // this GPU delivers for the four resources the PIR kernels are bounded by,
 // each measured with a plain loop rather than taken from the data sheet.
 //
-//   kind 0  HBM reads: every lane streams 16-byte non-temporal loads over a
-//           buffer far larger than the caches, summing the words mod 2^32
+//   kind 0  HBM reads: each workgroup streams its own contiguous share of a
+//           buffer far larger than the caches with 16-byte non-temporal
+//           loads, 16 in flight per lane, summing the words mod 2^32 (one
+//           256-lane workgroup per CU reads fastest; a grid-stride loop over
+//           the whole buffer, or more workgroups, read up to 15% slower)
 //   kind 1  VALU: 16 independent chains of v_xor_b32 per lane
 //   kind 2  LDS lookups: 8 independent chains of ds_read_b32 per lane, each
 //           address made from the previous load by one v_and_or_b32, in the
@@ -30,24 +33,27 @@ constexpr uint32_t PROBE_NT = 256; // lanes per workgroup (the LDS probe: 1024)
 constexpr uint32_t LDS_NT = 1024;
 constexpr uint32_t LDS_WORDS = 16384; // 256 rows of 64 words
 
+// workgroup b reads vectors [b n4 / blocks, (b + 1) n4 / blocks)
 __global__ __launch_bounds__(PROBE_NT) void k_peak_read(const uint32_t *__restrict__ in, uint64_t n4,
                                                         uint32_t *__restrict__ out)
 {
     typedef unsigned v4u __attribute__((ext_vector_type(4)));
+    constexpr uint32_t U = 16;
     const v4u *p = reinterpret_cast<const v4u *>(in);
-    const uint64_t stride = (uint64_t)gridDim.x * PROBE_NT;
-    uint64_t i = (uint64_t)blockIdx.x * PROBE_NT + threadIdx.x;
+    const uint64_t lo = (uint64_t)blockIdx.x * n4 / gridDim.x, hi = (uint64_t)(blockIdx.x + 1) * n4 / gridDim.x;
+    uint64_t i = lo + threadIdx.x;
     uint32_t acc = 0;
-    // four loads in flight per lane, then the tail one by one
-    for (; i + 3 * stride < n4; i += 4 * stride) {
-        const v4u a = __builtin_nontemporal_load(p + i);
-        const v4u b = __builtin_nontemporal_load(p + i + stride);
-        const v4u c = __builtin_nontemporal_load(p + i + 2 * stride);
-        const v4u d = __builtin_nontemporal_load(p + i + 3 * stride);
-        acc += (a.x + a.y + a.z + a.w) + (b.x + b.y + b.z + b.w) + (c.x + c.y + c.z + c.w) +
-               (d.x + d.y + d.z + d.w);
+    // U loads in flight per lane, then the tail one by one
+    for (; i + (U - 1) * PROBE_NT < hi; i += U * PROBE_NT) {
+        v4u v[U];
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++)
+            v[u] = __builtin_nontemporal_load(p + i + u * PROBE_NT);
+#pragma unroll
+        for (uint32_t u = 0; u < U; u++)
+            acc += (v[u].x + v[u].y) + (v[u].z + v[u].w);
     }
-    for (; i < n4; i += stride) {
+    for (; i < hi; i += PROBE_NT) {
         const v4u a = __builtin_nontemporal_load(p + i);
         acc += a.x + a.y + a.z + a.w;
     }
@@ -149,7 +155,8 @@ extern "C" {
 // Runs probe `kind` (0 HBM read, 1 VALU, 2 LDS, 3 int8 MFMA 16x16x64, 4 int8
 // MFMA 16x16x32) with `blocks` workgroups of 256 lanes (1024 for kind 2) on
 // `stream`; `iters` loop iterations per lane for kinds 1..4.  Kind 0 reads in_words words at d_in
-// (16-byte aligned, in_words a multiple of 4).  d_out receives one checksum
+// (16-byte aligned, in_words a multiple of 4), workgroup b the b-th of
+// `blocks` contiguous shares.  d_out receives one checksum
 // word per lane: blocks * 256 words (blocks * 1024 for kind 2).  Returns 0, -1
 // for bad arguments, -3 if the launch failed.
 int pir_peak_probe(uint32_t kind, uint32_t blocks, uint32_t iters, const uint32_t *d_in, uint64_t in_words,
@@ -157,7 +164,8 @@ int pir_peak_probe(uint32_t kind, uint32_t blocks, uint32_t iters, const uint32_
 {
     if (!d_out || blocks == 0 || kind > 4)
         return -1;
-    if (kind == 0 && (!d_in || in_words == 0 || in_words % 4 || ((uintptr_t)d_in % 16)))
+    if (kind == 0 && (!d_in || in_words == 0 || in_words % 4 || ((uintptr_t)d_in % 16) ||
+                      in_words / 4 > (UINT64_MAX >> 1) / blocks))
         return -1;
     hipStream_t st = (hipStream_t)stream;
     switch (kind) {

@@ -39,15 +39,22 @@ def run(eng, kind, blocks, iters, lanes, buf=None):
     return out.cpu().numpy().view(np.uint32)
 
 
+@pytest.mark.parametrize("blocks", [37, 256])
 @pytest.mark.parametrize("words", [4, 4 * 1000, 4 * 777777])
-def test_hbm_read_sums_the_buffer(eng, words):
+def test_hbm_read_sums_the_buffer(eng, words, blocks):
+    """Each workgroup's share sums to its lanes' checksums: the shares cover
+    the buffer once, also when it splits unevenly or has fewer 16-byte units
+    than there are workgroups."""
     import torch
 
     rng = np.random.default_rng(words)
     host = rng.integers(0, 1 << 32, words, dtype=np.uint64).astype(np.uint32)
     buf = torch.from_numpy(host.view(np.int32)).cuda()
-    got = run(eng, 0, 37, 0, 256, buf)
-    assert int(got.astype(np.uint64).sum()) & M32 == int(host.astype(np.uint64).sum()) & M32
+    got = run(eng, 0, blocks, 0, 256, buf).reshape(blocks, 256).astype(np.uint64)
+    n4 = words // 4
+    for b in range(blocks):
+        lo, hi = b * n4 // blocks, (b + 1) * n4 // blocks
+        assert int(got[b].sum()) & M32 == int(host[4 * lo:4 * hi].astype(np.uint64).sum()) & M32, b
 
 
 @pytest.mark.parametrize("iters", [1, 6, 101])

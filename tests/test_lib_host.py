@@ -405,6 +405,7 @@ def test_peak_probes_export_and_reject_bad_arguments():
     assert f(0, 1, 1, buf, 0, out, None) == -1                        # empty input
     assert f(0, 1, 1, buf, 1022, out, None) == -1                     # not whole 16-byte units
     assert f(0, 1, 1, ctypes.c_void_p(0x1004), 1024, out, None) == -1  # misaligned input
+    assert f(0, 1 << 20, 1, buf, 1 << 46, out, None) == -1            # shares past 64-bit offsets
 
 
 def test_too_much_work_is_refused_before_any_launch(lib):
