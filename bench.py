@@ -65,8 +65,13 @@ HBM_PEAK_GBS = 8000.0                # MI355X HBM3E, published
 KERNEL_SOURCES = ["paper_2301_10904_amd/csrc/pir_kernels.h", "paper_2301_10904_amd/csrc/aes_gfx950.h",
                   "paper_2301_10904_amd/csrc/aes_tables.h", "paper_2301_10904_amd/csrc/chacha_gfx950.h",
                   "paper_2301_10904_amd/csrc/quad_gfx950.h"]
-TRAFFIC_SUMMARY = {"aes128": ROOT / "profiles" / "k_pir_waves_2p20x64_b1024_traffic.json",
-                   "chacha20": ROOT / "profiles" / "k_pir_waves_chacha20_2p20x64_b1024_traffic.json"}
+# the committed counter summaries, by (PRF, log2 rows, keys per launch, row words)
+TRAFFIC_SUMMARY = {
+    ("aes128", 20, 1024, 64): ROOT / "profiles" / "k_pir_waves_2p20x64_b1024_traffic.json",
+    ("chacha20", 20, 1024, 64): ROOT / "profiles" / "k_pir_waves_chacha20_2p20x64_b1024_traffic.json",
+    ("aes128", 20, 1024, 128): ROOT / "profiles" / "k_pir_waves_2p20x128_b1024_traffic.json",
+    ("chacha20", 20, 1024, 128): ROOT / "profiles" / "k_pir_waves_chacha20_2p20x128_b1024_traffic.json",
+}
 
 
 def algorithmic_work(n: int, keys: int, dim: int, valu_product: bool = False, prf: str = "aes128"):
@@ -96,10 +101,14 @@ def kernel_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def measured_traffic(prf: str = "aes128"):
-    """HBM bytes per launch from the committed PMC summary, if the kernel is unchanged."""
+def measured_traffic(prf: str = "aes128", log_rows: int = 20, keys: int = 1024, dim: int = 64):
+    """HBM bytes per launch from the committed PMC summary of this workload, if
+    there is one and the kernel is unchanged since it was taken."""
+    path = TRAFFIC_SUMMARY.get((prf, log_rows, keys, dim))
+    if path is None:
+        return None
     try:
-        t = json.loads(TRAFFIC_SUMMARY[prf].read_text())
+        t = json.loads(path.read_text())
     except (OSError, ValueError):
         return None
     if t.get("kernel_digest") != kernel_digest():
@@ -299,7 +308,7 @@ def main():
     achieved = valu_ops / kern_s / 1e12
     peak = PEAK_INT32_OPS / 1e12
     roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(prf),
+                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(prf, n, B, dim),
                 "kernel": "k_pir_waves", "valu_ops_per_launch": valu_ops,
                 "avg_launch_ms": round(kern_s * 1e3, 4), "kernel_digest": kernel_digest()}
     # the fused kernel's tree nodes per second against the PRF engine alone

@@ -57,12 +57,18 @@ def test_kernel_digest_ignores_comments_and_layout(tmp_path, monkeypatch):
 
 
 def test_traffic_is_reported_only_for_the_profiled_kernel(tmp_path, monkeypatch):
-    """roofline.traffic is the stored counter figure while the kernel sources
-    hash to the digest stored with it, and null once they do not."""
+    """roofline.traffic is the stored counter figure of the same workload while
+    the kernel sources hash to the digest stored with it, and null once they do
+    not, or for a workload with no stored figure."""
     summary = tmp_path / "traffic.json"
-    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", {"aes128": summary})
+    monkeypatch.setattr(bench, "TRAFFIC_SUMMARY", {("aes128", 20, 1024, 64): summary})
     summary.write_text(json.dumps({"kernel_digest": bench.kernel_digest(), "bytes_per_launch": 123}))
     assert bench.measured_traffic("aes128") == 123
+    assert bench.measured_traffic("aes128", 20, 1024, 64) == 123
+    assert bench.measured_traffic("aes128", 20, 1024, 128) is None
+    assert bench.measured_traffic("aes128", 22, 1024, 64) is None
+    assert bench.measured_traffic("aes128", 20, 512, 64) is None
+    assert bench.measured_traffic("chacha20") is None
     summary.write_text(json.dumps({"kernel_digest": "0" * 16, "bytes_per_launch": 123}))
     assert bench.measured_traffic("aes128") is None
     summary.write_text("not json")
@@ -124,3 +130,13 @@ def test_pmc_summary_of_another_kernel(tmp_path):
     assert out["kernel"].startswith("k_pir_fused")
     assert out["counters_avg"] == {"FETCH_SIZE": 60.0, "WRITE_SIZE": 4.0}
     assert out["bytes_per_launch"] == 1024 * (60 * 2 + 4 * 1)
+
+
+def test_every_stored_counter_summary_names_its_workload():
+    """Each committed summary that roofline.traffic reads exists, and its note
+    names the table shape and PRF of the key it is stored under."""
+    for (prf, log_rows, keys, dim), path in bench.TRAFFIC_SUMMARY.items():
+        t = json.loads(path.read_text())
+        assert t["prf"] == prf and t["bytes_per_launch"] > 0
+        assert f"{keys} keys, 2^{log_rows} x {dim} table" in t["note"], path
+        assert (f"--dim {dim} " in t["command"]) == (dim != 64), path
