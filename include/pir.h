@@ -1,13 +1,13 @@
 /*
  * pir.h -- C ABI of the MI355X two-server DPF-PIR library (libpir.so).
  *
- * The calls follow the problem statement of the paper's section 3.1
- * ("Fundamentals of PIR and DPF"):
+ * The calls follow the problem statement of the paper's section 3.1 (the
+ * fundamentals of PIR and DPF):
  *   - the client runs Gen(1^lambda, alpha) -> (k_a, k_b)          : dpf_gen
  *   - each server computes T x Eval(k, {0 .. L-1}) over its table   : pir_answer,
  *     which fuses the full-domain evaluation of the node recurrence, Eq.
- *     (p1)-(p3), with the share-vector x table product (sections 3.2.3
- *     "memory-bounded tree traversal" and 3.2.4 "operator fusion")
+ *     (p1)-(p3), with the share-vector x table product (section 3.2.3,
+ *     the memory-bounded tree traversal, and 3.2.4, the fused product)
  *   - the client adds the two answers                                : pir_reconstruct
  *
  * Conventions
@@ -98,6 +98,7 @@ int dpf_gen_prf(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16
  *   d_keys     n_keys keys, key q at d_keys + q * key_stride (16-byte aligned,
  *              key_stride a multiple of 16 and >= dpf_key_size(n))
  *   d_table    row-major uint32 [rows][dim], 4-byte aligned, resident in HBM
+ *              (16-byte aligned tables are read with vector loads)
  *   rows       L, 1 <= rows <= 2^32; the keys' domain is n = ceil(log2 rows)
  *              (n = 1 when rows = 1) and every key header must carry that n
  *   dim        D, 1 <= dim <= PIR_MAX_DIM
@@ -105,8 +106,10 @@ int dpf_gen_prf(uint32_t n, uint64_t alpha, uint32_t beta, const uint8_t *seed16
  *              d_out[q][k] = sum_{j<rows} Eval(key_q, j) * T[j][k] mod 2^32
  *   stream     hipStream_t (void*), NULL for the default stream
  * Keys may be of either party and mixed in one call.  A key whose header is
- * bad (version, party, n or PRF id) gets an all-zero output row and raises
- * the flag read by pir_check_status().  n_keys = 0 is a no-op returning PIR_OK.
+ * bad (version, party, n or PRF id) gets an all-zero output row and sets
+ * PIR_STATUS_BAD_KEY in the call's status word (pir_workspace_status,
+ * pir_check_status).  n_keys = 0 is a no-op returning PIR_OK (the status
+ * word is left as it was).
  * Returns PIR_EINVAL on null pointers, bad sizes or misalignment (nothing is
  * launched), PIR_ENOMEM if the call's work items reach 2^31 (tens of
  * thousands of keys on a table of 2^32 rows), PIR_EHIP if a launch fails. */
@@ -116,7 +119,7 @@ int pir_answer(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride,
 
 /* pir_answer for keys of the PRF prf_id (section 3.2.6): every key of the
  * call must carry prf_id in byte 3, else it is treated as a bad header (zero
- * output row, flag for pir_check_status).  pir_answer is prf_id =
+ * output row, PIR_STATUS_BAD_KEY in the status word).  pir_answer is prf_id =
  * PIR_PRF_AES128.  PIR_EINVAL also for an unknown prf_id. */
 int pir_answer_prf(uint32_t prf_id, const uint8_t *d_keys, uint32_t n_keys,
                    uint32_t key_stride, const uint32_t *d_table, uint64_t rows,
@@ -144,7 +147,8 @@ int pir_answer_slice(uint32_t prf_id, uint32_t n, uint64_t row0, const uint8_t *
                      uint32_t key_stride, const uint32_t *d_table, uint64_t rows, uint32_t dim,
                      uint32_t *d_out, void *stream);
 
-/* One table of a multi-table call. */
+/* One table of a multi-table call (a batch grouped by table; the paper's
+ * batching of section 3.2.1 over tables of different sizes, section 3.2.5). */
 typedef struct {
     const uint32_t *d_table; /* row-major uint32 [rows][dim] in HBM */
     uint64_t rows;           /* L_t >= 1 */
@@ -153,7 +157,9 @@ typedef struct {
 } pir_table_t;
 
 /* Server side answer for keys over several tables of different sizes in one
- * stream-ordered call (a batch grouped by table).
+ * stream-ordered call (paper section 3.1: each key is answered as
+ * T_t x Eval(k, {0..L_t-1}) over its own table t; sections 3.2.1 and 3.2.5:
+ * one launch serves a batch of queries of uneven domain sizes).
  *   tables     host array of n_tables descriptors
  *   d_keys     all keys, grouped by table in the order of `tables`: the first
  *              tables[0].n_keys keys query table 0, and so on; key stride and
@@ -165,7 +171,8 @@ typedef struct {
 int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t *d_keys,
                      uint32_t key_stride, uint32_t *d_out, void *stream);
 
-/* pir_answer_multi for keys of the PRF prf_id, as pir_answer_prf. */
+/* pir_answer_multi for keys of the PRF prf_id (section 3.2.6), as
+ * pir_answer_prf. */
 int pir_answer_multi_prf(uint32_t prf_id, const pir_table_t *tables, uint32_t n_tables,
                          const uint8_t *d_keys, uint32_t key_stride, uint32_t *d_out,
                          void *stream);
@@ -227,13 +234,58 @@ typedef struct {
 } pir_plan_t;
 int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_plan_t *out);
 
+/* The work plan pir_answer_bins would use for a call over this one table
+ * (section 4.1: n_clients clients, one key per bin of 2^bin_log rows), for
+ * inspection and tests; it launches nothing and needs no GPU.  PIR_EINVAL for
+ * an unknown prf_id, no clients, or sizes pir_answer_bins rejects; PIR_ENOMEM
+ * where it would.  subtree_log is always in 1 .. bin_log. */
+int pir_plan_bins(uint32_t prf_id, uint64_t rows, uint32_t dim, uint32_t n_clients, uint32_t bin_log,
+                  pir_plan_t *out);
+
 /* Client side reconstruction (paper section 3.1): out[k] = a0[k] + a1[k]
  * mod 2^32 for k < dim; host buffers.  PIR_EINVAL on null pointers. */
 int pir_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim, uint32_t *out);
 
-/* After the caller has synchronised its answering streams: PIR_EKEY if any
- * key seen since the previous call had a bad header (and clears the flag),
- * else PIR_OK; PIR_EHIP if the flag cannot be read. */
+/* Call status (section 3.1: each server answers its own keys, so the report
+ * that a key was malformed belongs to the call that saw it).
+ *
+ * Every answer call (pir_answer*, pir_answer_slice, pir_answer_multi*,
+ * pir_answer_bins) reports into one 32-bit status word: its first kernel
+ * clears the word, in stream order, and a key with a bad header sets
+ * PIR_STATUS_BAD_KEY in it.  Once the call has completed, the word holds that
+ * call's status.  The word is the first word of the status workspace:
+ *   - the workspace the calling host thread bound with pir_set_workspace, or
+ *   - if it bound none, the library's own workspace on the current device (a
+ *     static device array; nothing is ever allocated), read by
+ *     pir_check_status().  That one is shared by every thread and stream of
+ *     the process: calls that overlap in time on one device overwrite each
+ *     other's status in it, so concurrent streams should each bind their own.
+ * The calls clear the word with a kernel, never a memset, so they may be
+ * captured in a HIP graph; a replay reports its own status. */
+#define PIR_WORKSPACE_BYTES 256u  /* size of a status workspace */
+#define PIR_STATUS_BAD_KEY 1u     /* status bit: a key had a bad header */
+
+/* Bytes of a status workspace: PIR_WORKSPACE_BYTES. */
+size_t pir_workspace_size(void);
+
+/* Binds d_ws, a device buffer of at least pir_workspace_size() bytes,
+ * 16-byte aligned, on the device the calls will run on, as the status
+ * workspace of the answer calls this host thread makes from now on; NULL
+ * unbinds (back to the library's own).  The caller owns the buffer and keeps
+ * it alive while calls that use it may run; it needs no initialisation.
+ * PIR_EINVAL for a short or misaligned buffer (the binding is unchanged). */
+int pir_set_workspace(void *d_ws, size_t bytes);
+
+/* The status of the last call that used workspace d_ws, in the order of
+ * `stream`: enqueues a read of the word on `stream` and waits for it, so the
+ * calls enqueued on `stream` before have completed.  PIR_EKEY if that call
+ * saw a key with a bad header (version, party, n or PRF id), else PIR_OK;
+ * PIR_EINVAL for a null or misaligned d_ws; PIR_EHIP if the read fails. */
+int pir_workspace_status(const void *d_ws, void *stream);
+
+/* After the caller has synchronised the stream of the last call that used the
+ * library's own workspace on the current device: PIR_EKEY if that call saw a
+ * key with a bad header, else PIR_OK; PIR_EHIP if the word cannot be read. */
 int pir_check_status(void);
 
 /* Static, NUL-terminated description of a status code. */

@@ -5,10 +5,10 @@
  * benchmark's CPU-baseline leg may load this library.  The product path
  * (include/pir.h and the package) shares no code with it and never calls it.
  *
- * What it computes (paper section 3.1, "Fundamentals of PIR and DPF"):
+ * What it computes (paper section 3.1, the fundamentals of PIR and DPF):
  *   - PRF_s(x): AES-128 under key s (FIPS-197), used in counter mode: the
- *     plaintext is the 128-bit big-endian integer x (the paper's PRF table
- *     lists AES-128 as "block cipher (ctr mode)").
+ *     plaintext is the 128-bit big-endian integer x (the paper's PRF table,
+ *     Table 5, runs AES-128 as a block cipher in counter mode).
  *   - Eval(k, j): the node recurrence of Eq. (p1)-(p3),
  *       P(0,0)  = root of the key,
  *       P(d,j)  = PRF_{P(d-1,j/2)}(j mod 2) XOR C_{t(P(d-1,j/2))}[j mod 2, d],

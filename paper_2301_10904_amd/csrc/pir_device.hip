@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <mutex>
 #include <vector>
 
 #include "pir.h"
@@ -21,15 +23,20 @@ static uint32_t ceil_log2(uint64_t x)
     return r;
 }
 
+// Rows are read with 16-byte (or 8-byte) vector loads only from a table whose
+// base is 16-byte aligned; a table at any other 4-byte boundary takes the
+// instantiations that read single words.
+static bool vec_aligned(const uint32_t *d_table) { return (uintptr_t)d_table % 16 == 0; }
+
 template <class PRF, int Q>
 static void launch_q(uint32_t kch, dim3 grid, hipStream_t st, const uint8_t *keys, uint32_t n_keys,
                      uint32_t stride, const uint32_t *table, uint64_t rows, uint32_t dim, uint32_t *out,
-                     const Geometry &g)
+                     const Geometry &g, uint32_t *status)
 {
 #define PIR_LAUNCH_FUSED(KCH, V4, S)                                                                              \
     hipLaunchKernelGGL((k_pir_fused<PRF, Q, KCH, V4, S>), grid, dim3(NT), 0, st, keys, n_keys, stride, table, rows,  \
-                       dim, out, g)
-    const bool v4 = dim % 4 == 0;
+                       dim, out, g, status)
+    const bool v4 = dim % 4 == 0 && vec_aligned(table);
     if constexpr (Q == 1) {
         // one key streams the table once per call: past the size of the
         // memory-side cache (256 MiB) its rows are read without allocating in
@@ -70,6 +77,64 @@ static int fail_hip(hipError_t e)
     return PIR_EHIP;
 }
 
+// The library's own status workspace, one per device: used by calls from a
+// thread that has bound no workspace of its own (pir_set_workspace).  Host
+// code never names the array itself: its device address comes from
+// hipGetSymbolAddress, once per device with that device current.
+static __device__ __align__(256) uint32_t scratch[PIR_WORKSPACE_BYTES / 4];
+constexpr int MAX_DEVICES = 64;
+static std::atomic<uint32_t *> g_scratch_ptr[MAX_DEVICES];
+static std::mutex g_scratch_mu;
+
+static uint32_t *default_workspace()
+{
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess || dev < 0 || dev >= MAX_DEVICES) {
+        pir_impl::set_hip_error((int)(e != hipSuccess ? e : hipErrorInvalidDevice));
+        return nullptr;
+    }
+    if (uint32_t *p = g_scratch_ptr[dev].load(std::memory_order_acquire))
+        return p;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (uint32_t *p = g_scratch_ptr[dev].load(std::memory_order_relaxed))
+        return p;
+    uint32_t *p = nullptr;
+    e = hipGetSymbolAddress((void **)&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) {
+        pir_impl::set_hip_error((int)(e != hipSuccess ? e : hipErrorInvalidSymbol));
+        return nullptr;
+    }
+    g_scratch_ptr[dev].store(p, std::memory_order_release);
+    return p;
+}
+
+// The workspace bound by this thread (pir_set_workspace), or null.
+static thread_local uint32_t *t_workspace = nullptr;
+
+// Per-call state: the status word the call's kernels report into, located on
+// first use (so that argument errors are found without touching the GPU), and
+// cleared by the call's first launch.
+struct CallCtx {
+    uint32_t *status = nullptr;
+    bool cleared = false;
+    // The status word, or null if the default workspace cannot be located.
+    uint32_t *word()
+    {
+        if (!status)
+            status = t_workspace ? t_workspace : default_workspace();
+        return status;
+    }
+    // For the first k_fill_zero of the call: the word to clear, then null.
+    uint32_t *clear_once()
+    {
+        if (cleared)
+            return nullptr;
+        cleared = true;
+        return status;
+    }
+};
+
 constexpr uint64_t WAVE_SLOTS = 256 * 16; // waves resident at once: 256 CUs x two 8-wave workgroups
 
 // Subtree height of a single-table wave launch.  A lane's work per item is its
@@ -98,13 +163,19 @@ static uint32_t wave_height(uint64_t n_bins, uint64_t bin_rows, uint64_t groups,
     return best_h;
 }
 
+// Largest subtree height of a wave item whose rows lie in an aligned subtree
+// of height m (1 <= m <= n): at most what the path registers allow (HMAX3),
+// and m - 2 where m >= 3, so that the item's four subtrees fill it; below that
+// (a bin or slice of at most 4 rows) subtrees of height 1, whose unused lanes
+// are inactive.  Always 1 <= h <= m <= n, which the kernel relies on.
+static uint32_t wave_hmax(uint32_t m) { return m >= 3 ? std::min<uint32_t>(HMAX3, m - 2) : 1u; }
+
 // Work plan of a wave-kernel launch over `count` tasks: fills h, n_groups,
 // chunks_per_bin and item_begin of every task and returns the number of wave
-// items (0 if it reaches 2^31).  The subtree height h is at most what the path
-// registers allow (HMAX3) and m - 2 (a bin, or the aligned subtree holding a
-// table slice, of height m holds four subtrees); a single
-// table gets the height of wave_height(), a launch of several tables the
-// largest (the tables together fill the GPU).
+// items (0 if it reaches 2^31).  The subtree height h is at most
+// wave_hmax(m) for the aligned subtree of height m holding a bin (or a table
+// slice); a single table gets the height of wave_height(), a launch of several
+// tables the largest (the tables together fill the GPU).
 static uint64_t plan_waves(WaveTask *ts, uint32_t count)
 {
     uint64_t items = 0;
@@ -116,7 +187,7 @@ static uint64_t plan_waves(WaveTask *ts, uint32_t count)
         // a slice of a table lies in an aligned subtree of height m < n, and a
         // lane's subtree must lie in it too; whole tables and bins have m = n
         const uint32_t m = std::min<uint32_t>(t.n, bin_rows <= 2 ? 1 : ceil_log2(bin_rows));
-        const uint32_t hmax = std::min<uint32_t>(HMAX3, m - 2);
+        const uint32_t hmax = wave_hmax(m);
         const uint32_t h = count == 1 ? wave_height(t.n_bins, bin_rows, t.n_groups, t.n, hmax) : hmax;
         t.h = h;
         t.chunks_per_bin = (uint32_t)chunks_per_bin(h);
@@ -128,10 +199,26 @@ static uint64_t plan_waves(WaveTask *ts, uint32_t count)
     return items;
 }
 
-// Wave-kernel launch for up to MAX_TASKS tables of one column class (KT, VEC).
-// Plans the tasks and clears their outputs first.
+// Column class of the wave kernel, which picks its instantiation (KT, VEC):
+// tables in one launch must share it.  The vector-load classes 0..2 need a
+// 16-byte aligned table; others of those widths read single words.
+static int wave_class(uint32_t dim, bool aligned)
+{
+    if (dim == 64 && aligned) return 0;
+    if (dim == 32 && aligned) return 1;
+    if (dim == 16 && aligned) return 2;
+    if (dim <= 16) return 3;
+    if (dim <= 32) return 4;
+    if (dim <= 64) return 5;
+    if (dim <= 128) return 6;
+    return -1;
+}
+constexpr int WAVE_CLASSES = 7;
+
+// Wave-kernel launch for up to MAX_TASKS tables of column class cls.  Plans
+// the tasks and clears their outputs first.
 template <class PRF>
-static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipStream_t st)
+static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, int cls, CallCtx &ctx, hipStream_t st)
 {
     WaveTasks W;
     bool any = false;
@@ -140,50 +227,35 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, hipSt
     const uint64_t items = plan_waves(ts, count);
     if (items == 0 && any)
         return PIR_ENOMEM;
+    if (!ctx.word())
+        return PIR_EHIP;
     for (uint32_t i = 0; i < count; i++)
         W.t[i] = ts[i];
     W.count = count;
     W.n_items = (uint32_t)items;
+    W.status = ctx.status;
     for (uint32_t i = 0; i < count; i++) {
         const size_t words = (size_t)ts[i].n_keys * ts[i].n_bins * ts[i].dim;
-        const uint32_t blocks = (uint32_t)std::min<size_t>((words + 255) / 256, 4096);
-        hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, ts[i].out, words);
+        const uint32_t blocks = (uint32_t)std::max<size_t>(1, std::min<size_t>((words + 255) / 256, 4096));
+        hipLaunchKernelGGL(k_fill_zero, dim3(blocks), dim3(256), 0, st, ts[i].out, words, ctx.clear_once());
     }
     if (items == 0)
         return PIR_OK;
     const dim3 grid((uint32_t)((items + NW3 - 1) / NW3));
-    const uint32_t dim = ts[0].dim;
 #define PIR_LAUNCH_WAVES(KT, VEC) hipLaunchKernelGGL((k_pir_waves<PRF, KT, VEC>), grid, dim3(NT3), 0, st, W, key_stride)
-    if (dim > 64)
-        PIR_LAUNCH_WAVES(8, false);
-    else if (dim == 64)
-        PIR_LAUNCH_WAVES(4, true);
-    else if (dim == 32)
-        PIR_LAUNCH_WAVES(2, true);
-    else if (dim == 16)
-        PIR_LAUNCH_WAVES(1, true);
-    else if (dim < 16)
-        PIR_LAUNCH_WAVES(1, false);
-    else if (dim < 32)
-        PIR_LAUNCH_WAVES(2, false);
-    else
-        PIR_LAUNCH_WAVES(4, false);
+    switch (cls) {
+    case 0: PIR_LAUNCH_WAVES(4, true); break;
+    case 1: PIR_LAUNCH_WAVES(2, true); break;
+    case 2: PIR_LAUNCH_WAVES(1, true); break;
+    case 3: PIR_LAUNCH_WAVES(1, false); break;
+    case 4: PIR_LAUNCH_WAVES(2, false); break;
+    case 5: PIR_LAUNCH_WAVES(4, false); break;
+    case 6: PIR_LAUNCH_WAVES(8, false); break;
+    default: return PIR_EINVAL;
+    }
 #undef PIR_LAUNCH_WAVES
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? PIR_OK : fail_hip(e);
-}
-
-// Column class of the wave kernel: tables in one launch must share it.
-static int wave_class(uint32_t dim)
-{
-    if (dim == 64) return 0;
-    if (dim == 32) return 1;
-    if (dim == 16) return 2;
-    if (dim < 16) return 3;
-    if (dim < 32) return 4;
-    if (dim <= 64) return 5;
-    if (dim <= 128) return 6;
-    return -1;
 }
 
 // Which kernel answers one table: the wave kernel (int8 matrix cores, up to 16
@@ -319,7 +391,8 @@ static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32
 // enqueues its kernels.
 template <class PRF>
 static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, uint32_t n, uint64_t row0,
-                        const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out, hipStream_t st)
+                        const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out, CallCtx &ctx,
+                        hipStream_t st)
 {
     if (n_keys == 0)
         return PIR_OK;
@@ -336,11 +409,11 @@ static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_str
 
     if (const uint32_t tail = split_tail(n_keys, m)) {
         const uint32_t head = n_keys - tail;
-        const int rc = answer_range<PRF>(d_keys, head, key_stride, n, row0, d_table, rows, dim, d_out, st);
+        const int rc = answer_range<PRF>(d_keys, head, key_stride, n, row0, d_table, rows, dim, d_out, ctx, st);
         if (rc != PIR_OK)
             return rc;
         return answer_range<PRF>(d_keys + (size_t)head * key_stride, tail, key_stride, n, row0, d_table, rows, dim,
-                                 d_out + (size_t)head * dim, st);
+                                 d_out + (size_t)head * dim, ctx, st);
     }
 
     if (use_wave_kernel(PRF::id, n_keys, m, dim)) {
@@ -354,7 +427,7 @@ static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_str
         t.n_keys = n_keys;
         t.n = n;
         t.n_bins = 1;
-        return launch_waves<PRF>(&t, 1, key_stride, st);
+        return launch_waves<PRF>(&t, 1, key_stride, wave_class(dim, vec_aligned(d_table)), ctx, st);
     }
 
     const FusedPlan p = plan_fused(n_keys, rows, dim, n, m, row0);
@@ -363,16 +436,19 @@ static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_str
     const Geometry &g = p.g;
     const uint32_t Q = p.Q, kch = p.kch;
 
+    if (!ctx.word())
+        return PIR_EHIP;
+    uint32_t *const status = ctx.status;
     const size_t count = (size_t)n_keys * dim;
-    const uint32_t fill_blocks = (uint32_t)std::min<size_t>((count + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks), dim3(256), 0, st, d_out, count);
+    const uint32_t fill_blocks = (uint32_t)std::max<size_t>(1, std::min<size_t>((count + 255) / 256, 4096));
+    hipLaunchKernelGGL(k_fill_zero, dim3(fill_blocks), dim3(256), 0, st, d_out, count, ctx.clear_once());
     const dim3 grid((uint32_t)p.grid);
     switch (Q) {
-    case 1: launch_q<PRF, 1>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
-    case 2: launch_q<PRF, 2>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
-    case 4: launch_q<PRF, 4>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
-    case 8: launch_q<PRF, 8>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
-    default: launch_q<PRF, 16>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g); break;
+    case 1: launch_q<PRF, 1>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g, status); break;
+    case 2: launch_q<PRF, 2>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g, status); break;
+    case 4: launch_q<PRF, 4>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g, status); break;
+    case 8: launch_q<PRF, 8>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g, status); break;
+    default: launch_q<PRF, 16>(kch, grid, st, d_keys, n_keys, key_stride, d_table, rows, dim, d_out, g, status); break;
     }
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? PIR_OK : fail_hip(e);
@@ -381,18 +457,19 @@ static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_str
 // One whole table.
 template <class PRF>
 static int answer_one(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride, const uint32_t *d_table,
-                      uint64_t rows, uint32_t dim, uint32_t *d_out, hipStream_t st)
+                      uint64_t rows, uint32_t dim, uint32_t *d_out, CallCtx &ctx, hipStream_t st)
 {
     if (rows == 0 || rows > ((uint64_t)1 << PIR_MAX_LOG_DOMAIN))
         return n_keys == 0 ? PIR_OK : PIR_EINVAL;
     const uint32_t n = rows <= 2 ? 1 : ceil_log2(rows);
-    return answer_range<PRF>(d_keys, n_keys, key_stride, n, 0, d_table, rows, dim, d_out, st);
+    return answer_range<PRF>(d_keys, n_keys, key_stride, n, 0, d_table, rows, dim, d_out, ctx, st);
 }
 
 template <class PRF>
 static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t *d_keys, uint32_t key_stride,
                         uint32_t *d_out, void *stream)
 {
+    CallCtx ctx;
     if (!tables && n_tables)
         return PIR_EINVAL;
     // validate every descriptor before anything is enqueued
@@ -411,7 +488,7 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
     // tables the wave kernel takes go out grouped by column class, up to
     // MAX_TASKS per launch; the rest one by one, and the remainders split off
     // large tables after the wave launches
-    std::vector<WaveTask> cls[7];
+    std::vector<WaveTask> cls[WAVE_CLASSES];
     struct Tail {
         uint32_t table, n_keys; // the last n_keys keys of table `table`, at keys, answered into out
         const uint8_t *keys;
@@ -428,7 +505,7 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
         if (T.n_keys == 0)
             continue;
         const uint32_t n = T.rows <= 2 ? 1 : ceil_log2(T.rows);
-        const int c = wave_class(T.dim);
+        const int c = wave_class(T.dim, vec_aligned(T.d_table));
         if (n >= 3 && c >= 0) { // several tables share a launch, so even small batches go to waves
             const uint32_t tail = multi_tail(T.n_keys, n);
             const uint32_t head = T.n_keys - tail;
@@ -447,21 +524,23 @@ static int answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint
             if (tail)
                 tails.push_back({t, tail, kp + (size_t)head * key_stride, op + (size_t)head * T.dim});
         } else {
-            int st = answer_one<PRF>(kp, T.n_keys, key_stride, T.d_table, T.rows, T.dim, op, (hipStream_t)stream);
+            int st = answer_one<PRF>(kp, T.n_keys, key_stride, T.d_table, T.rows, T.dim, op, ctx,
+                                     (hipStream_t)stream);
             if (st != PIR_OK)
                 return st;
         }
     }
-    for (auto &v : cls)
-        for (size_t i = 0; i < v.size(); i += MAX_TASKS) {
-            const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, v.size() - i);
-            int st = launch_waves<PRF>(v.data() + i, cnt, key_stride, (hipStream_t)stream);
+    for (int c = 0; c < WAVE_CLASSES; c++)
+        for (size_t i = 0; i < cls[c].size(); i += MAX_TASKS) {
+            const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, cls[c].size() - i);
+            int st = launch_waves<PRF>(cls[c].data() + i, cnt, key_stride, c, ctx, (hipStream_t)stream);
             if (st != PIR_OK)
                 return st;
         }
     for (const Tail &r : tails) {
         const pir_table_t &T = tables[r.table];
-        int st = answer_one<PRF>(r.keys, r.n_keys, key_stride, T.d_table, T.rows, T.dim, r.out, (hipStream_t)stream);
+        int st = answer_one<PRF>(r.keys, r.n_keys, key_stride, T.d_table, T.rows, T.dim, r.out, ctx,
+                                 (hipStream_t)stream);
         if (st != PIR_OK)
             return st;
     }
@@ -474,6 +553,7 @@ template <class PRF>
 static int answer_bins(const pir_bins_t *tables, uint32_t n_tables, const uint8_t *d_keys, uint32_t key_stride,
                        uint32_t *d_out, void *stream)
 {
+    CallCtx ctx;
     if (!tables && n_tables)
         return PIR_EINVAL;
     for (uint32_t t = 0; t < n_tables; t++) {
@@ -488,7 +568,7 @@ static int answer_bins(const pir_bins_t *tables, uint32_t n_tables, const uint8_
             ((uintptr_t)T.d_table % 4) || ((uintptr_t)d_out % 4))
             return PIR_EINVAL;
     }
-    std::vector<WaveTask> cls[7];
+    std::vector<WaveTask> cls[WAVE_CLASSES];
     size_t key_off = 0, out_off = 0;
     for (uint32_t t = 0; t < n_tables; t++) {
         const pir_bins_t &T = tables[t];
@@ -508,12 +588,12 @@ static int answer_bins(const pir_bins_t *tables, uint32_t n_tables, const uint8_
         w.n_keys = T.n_clients;
         w.n = T.bin_log;
         w.n_bins = (uint32_t)n_bins;
-        cls[wave_class(T.dim)].push_back(w);
+        cls[wave_class(T.dim, vec_aligned(T.d_table))].push_back(w);
     }
-    for (auto &v : cls)
-        for (size_t i = 0; i < v.size(); i += MAX_TASKS) {
-            const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, v.size() - i);
-            int st = launch_waves<PRF>(v.data() + i, cnt, key_stride, (hipStream_t)stream);
+    for (int c = 0; c < WAVE_CLASSES; c++)
+        for (size_t i = 0; i < cls[c].size(); i += MAX_TASKS) {
+            const uint32_t cnt = (uint32_t)std::min<size_t>(MAX_TASKS, cls[c].size() - i);
+            int st = launch_waves<PRF>(cls[c].data() + i, cnt, key_stride, c, ctx, (hipStream_t)stream);
             if (st != PIR_OK)
                 return st;
         }
@@ -573,6 +653,36 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
     return PIR_OK;
 }
 
+int pir_plan_bins(uint32_t prf_id, uint64_t rows, uint32_t dim, uint32_t n_clients, uint32_t bin_log,
+                  pir_plan_t *out)
+{
+    if (!out || (prf_id != PIR_PRF_AES128 && prf_id != PIR_PRF_CHACHA20) || n_clients == 0 || rows == 0 ||
+        dim == 0 || dim > PIR_BINS_MAX_DIM || rows > ((uint64_t)1 << PIR_MAX_LOG_DOMAIN) ||
+        bin_log < PIR_BINS_MIN_LOG || bin_log > PIR_MAX_LOG_DOMAIN)
+        return PIR_EINVAL;
+    WaveTask t{};
+    t.rows = rows;
+    t.dim = dim;
+    t.n_keys = n_clients;
+    t.n = bin_log;
+    t.n_bins = (uint32_t)((rows + ((uint64_t)1 << bin_log) - 1) >> bin_log);
+    const uint64_t items = plan_waves(&t, 1);
+    if (items == 0)
+        return PIR_ENOMEM;
+    *out = pir_plan_t{};
+    out->kernel = PIR_KERNEL_WAVES;
+    out->n = bin_log;
+    out->items = items;
+    out->workgroups = (items + NW3 - 1) / NW3;
+    out->lanes_per_workgroup = NT3;
+    out->lds_bytes = prf_id == PIR_PRF_AES128 ? AES_TAB_WORDS * 4 : 0;
+    out->keys_per_item = 16;
+    out->subtree_log = t.h;
+    out->rows_per_item = (uint64_t)4 << t.h;
+    out->descent_levels = bin_log - t.h;
+    return PIR_OK;
+}
+
 int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables, const uint8_t *d_keys,
                     uint32_t key_stride, uint32_t *d_out, void *stream)
 {
@@ -586,10 +696,12 @@ int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables
 int pir_answer_prf(uint32_t prf_id, const uint8_t *d_keys, uint32_t n_keys, uint32_t key_stride,
                    const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out, void *stream)
 {
+    CallCtx ctx;
+    const hipStream_t st = (hipStream_t)stream;
     if (prf_id == PIR_PRF_AES128)
-        return answer_one<AesPrf>(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, (hipStream_t)stream);
+        return answer_one<AesPrf>(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, ctx, st);
     if (prf_id == PIR_PRF_CHACHA20)
-        return answer_one<ChaChaPrf>(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, (hipStream_t)stream);
+        return answer_one<ChaChaPrf>(d_keys, n_keys, key_stride, d_table, rows, dim, d_out, ctx, st);
     return PIR_EINVAL;
 }
 
@@ -597,11 +709,12 @@ int pir_answer_slice(uint32_t prf_id, uint32_t n, uint64_t row0, const uint8_t *
                      uint32_t key_stride, const uint32_t *d_table, uint64_t rows, uint32_t dim, uint32_t *d_out,
                      void *stream)
 {
+    CallCtx ctx;
     const hipStream_t st = (hipStream_t)stream;
     if (prf_id == PIR_PRF_AES128)
-        return answer_range<AesPrf>(d_keys, n_keys, key_stride, n, row0, d_table, rows, dim, d_out, st);
+        return answer_range<AesPrf>(d_keys, n_keys, key_stride, n, row0, d_table, rows, dim, d_out, ctx, st);
     if (prf_id == PIR_PRF_CHACHA20)
-        return answer_range<ChaChaPrf>(d_keys, n_keys, key_stride, n, row0, d_table, rows, dim, d_out, st);
+        return answer_range<ChaChaPrf>(d_keys, n_keys, key_stride, n, row0, d_table, rows, dim, d_out, ctx, st);
     return PIR_EINVAL;
 }
 
@@ -629,18 +742,38 @@ int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t
 
 int pir_check_status(void)
 {
+    uint32_t *p = default_workspace();
+    if (!p)
+        return PIR_EHIP;
     uint32_t v = 0;
-    hipError_t e = hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_key_error), sizeof v, 0, hipMemcpyDeviceToHost);
+    const hipError_t e = hipMemcpy(&v, p, sizeof v, hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return fail_hip(e);
-    if (v) {
-        v = 0;
-        e = hipMemcpyToSymbol(HIP_SYMBOL(g_key_error), &v, sizeof v, 0, hipMemcpyHostToDevice);
-        if (e != hipSuccess)
-            return fail_hip(e);
-        return PIR_EKEY;
-    }
+    return (v & PIR_STATUS_BAD_KEY) ? PIR_EKEY : PIR_OK;
+}
+
+size_t pir_workspace_size(void) { return PIR_WORKSPACE_BYTES; }
+
+int pir_set_workspace(void *d_ws, size_t bytes)
+{
+    if (d_ws && (bytes < PIR_WORKSPACE_BYTES || (uintptr_t)d_ws % 16))
+        return PIR_EINVAL;
+    t_workspace = static_cast<uint32_t *>(d_ws);
     return PIR_OK;
+}
+
+int pir_workspace_status(const void *d_ws, void *stream)
+{
+    if (!d_ws || (uintptr_t)d_ws % 16)
+        return PIR_EINVAL;
+    const hipStream_t st = (hipStream_t)stream;
+    uint32_t v = 0;
+    hipError_t e = hipMemcpyAsync(&v, d_ws, sizeof v, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess)
+        e = hipStreamSynchronize(st);
+    if (e != hipSuccess)
+        return fail_hip(e);
+    return (v & PIR_STATUS_BAD_KEY) ? PIR_EKEY : PIR_OK;
 }
 
 } // extern "C"

@@ -55,7 +55,6 @@ constexpr int HMAX = 10;     // largest per-lane subtree height
 constexpr int QMAX = 16;     // keys per workgroup
 
 __constant__ pir_aes::Words256 c_TE = pir_aes::TE;
-__device__ uint32_t g_key_error;
 
 struct Seed {
     uint32_t w[4];
@@ -139,27 +138,51 @@ struct KeyView {
         uint4 v = *reinterpret_cast<const uint4 *>(p + 16);
         return Seed{{v.x, v.y, v.z, v.w}};
     }
+};
+
+// The codewords of a key, C_t[c, d] for d = 1..n, read from the key in HBM
+// (CwGlobal) or from a copy in LDS (CwLds); both point at C_0[0, 1].  The
+// casts keep the pointer's address space, so LDS copies are read with ds_read.
+typedef unsigned v4u __attribute__((ext_vector_type(4)));
+template <class Byte, class V4, class U32>
+struct CwViewT {
+    Byte *p;
+    __device__ __forceinline__ uint4 vec(size_t off) const
+    {
+        const v4u x = *(V4 *)(p + off);
+        return make_uint4(x.x, x.y, x.z, x.w);
+    }
     // C_t[0, d] and C_t[1, d]
     __device__ __forceinline__ void cw(uint32_t d, uint32_t t, uint4 &c0, uint4 &c1) const
     {
-        const uint4 *q = reinterpret_cast<const uint4 *>(p + 32 + 64 * (size_t)(d - 1) + 32 * t);
-        c0 = q[0];
-        c1 = q[1];
+        c0 = vec(64 * (size_t)(d - 1) + 32 * t);
+        c1 = vec(64 * (size_t)(d - 1) + 32 * t + 16);
+    }
+    __device__ __forceinline__ uint4 one(uint32_t d, uint32_t t, uint32_t c) const
+    {
+        return vec(64 * (size_t)(d - 1) + 32 * t + 16 * c);
+    }
+    // word w of C_t[c, d]
+    __device__ __forceinline__ uint32_t word(uint32_t d, uint32_t t, uint32_t c, uint32_t w) const
+    {
+        return *(U32 *)(p + 64 * (size_t)(d - 1) + 32 * t + 16 * c + 4 * w);
     }
     __device__ __forceinline__ uint2 cw_word0(uint32_t d, uint32_t t) const
     {
-        const uint32_t *q = reinterpret_cast<const uint32_t *>(p + 32 + 64 * (size_t)(d - 1) + 32 * t);
-        return make_uint2(q[0], q[4]);
+        return make_uint2(word(d, t, 0, 0), word(d, t, 1, 0));
     }
 };
+typedef const __attribute__((address_space(3))) v4u lds_v4u;
+typedef CwViewT<const uint8_t, const v4u, const uint32_t> CwGlobal;
+typedef CwViewT<lds_u8, lds_v4u, lds_u32> CwLds;
+__device__ __forceinline__ CwGlobal cw_global(const KeyView &K) { return CwGlobal{K.p + 32}; }
 
 // Both children of the node with seed s, codeword level d (Eq. (p3)).
-template <class PRF>
-__device__ __forceinline__ void children(const PRF &P, const KeyView &K, const Seed &s, uint32_t d, Seed &c0,
-                                         Seed &c1)
+template <class PRF, class CW>
+__device__ __forceinline__ void children(const PRF &P, const CW &C, const Seed &s, uint32_t d, Seed &c0, Seed &c1)
 {
     uint4 w0, w1;
-    K.cw(d, s.w[0] & 1u, w0, w1);
+    C.cw(d, s.w[0] & 1u, w0, w1);
     uint32_t a[4], b[4];
     P.pair(s.w, a, b);
     c0 = Seed{{a[0] ^ w0.x, a[1] ^ w0.y, a[2] ^ w0.z, a[3] ^ w0.w}};
@@ -167,11 +190,10 @@ __device__ __forceinline__ void children(const PRF &P, const KeyView &K, const S
 }
 
 // Child c of the node with seed s, codeword level d (Eq. (p3)), for descents.
-template <class PRF>
-__device__ __forceinline__ Seed child_on_path(const PRF &P, const KeyView &K, const Seed &s, uint32_t d, uint32_t c)
+template <class PRF, class CW>
+__device__ __forceinline__ Seed child_on_path(const PRF &P, const CW &C, const Seed &s, uint32_t d, uint32_t c)
 {
-    const uint4 *q = reinterpret_cast<const uint4 *>(K.p + 32 + 64 * (size_t)(d - 1) + 32 * (s.w[0] & 1u) + 16 * c);
-    const uint4 w = *q;
+    const uint4 w = C.one(d, s.w[0] & 1u, c);
     uint32_t a[4];
     P.one(s.w, c, a);
     return Seed{{a[0] ^ w.x, a[1] ^ w.y, a[2] ^ w.z, a[3] ^ w.w}};
@@ -190,8 +212,13 @@ __device__ __forceinline__ uint32_t xcd_block()
     return x * per + (x < extra ? x : extra) + k;
 }
 
-__global__ __attribute__((unused)) void k_fill_zero(uint32_t *out, size_t count)
+// Clears out[0 .. count) and, if status is not null, the call's status word
+// (the first launch of every call clears it, in stream order before the
+// kernels that may set it).
+__global__ __attribute__((unused)) void k_fill_zero(uint32_t *out, size_t count, uint32_t *status)
 {
+    if (status && blockIdx.x == 0 && threadIdx.x == 0)
+        *status = 0;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     size_t stride = (size_t)gridDim.x * blockDim.x;
     for (; i < count; i += stride)
@@ -331,15 +358,22 @@ __device__ __forceinline__ uint4 row_load4(const uint32_t *p)
 }
 
 // Q keys per group (Q <= QMAX); KCH column chunks of 64 (dim <= 64 KCH);
-// VEC4: dim is a multiple of 4 (16-byte row segments are aligned); STREAM:
+// VEC4: dim is a multiple of 4 and the table 16-byte aligned (16-byte row
+// segments are aligned); STREAM:
 // table rows are read with row_load4<true> (single keys on large tables).
 template <class PRF, int Q, int KCH, bool VEC4, bool STREAM>
 __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ keys, uint32_t n_keys,
                                                   uint32_t stride, const uint32_t *__restrict__ table,
                                                   uint64_t rows, uint32_t dim, uint32_t *__restrict__ out,
-                                                  Geometry g)
+                                                  Geometry g, uint32_t *status)
 {
     __shared__ Smem<PRF::TAB_WORDS> sm;
+    // CWL: one or two keys per workgroup keep their codewords in LDS (2 KiB
+    // each at most), so that the dependent chain of node evaluations from the
+    // root down never waits on a load from memory
+    constexpr bool CWL = Q <= 2;
+    constexpr uint32_t CW_WORDS = 64 * PIR_MAX_LOG_DOMAIN / 4; // one key's codewords
+    __shared__ uint4 s_cw[CWL ? Q * CW_WORDS / 4 : 1];
 
     const uint32_t tid = threadIdx.x;
     const uint32_t lane = tid & 63, wave = tid >> 6;
@@ -348,6 +382,24 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     const uint32_t chunk = blk / g.n_groups;
     const uint64_t row_base = (uint64_t)chunk << g.H;
     const PRF P(sm.tab, lane);
+
+    if constexpr (CWL) {
+        // key q's 4n codeword vectors to s_cw[q CW_WORDS / 4 ..]; a key past
+        // the batch leaves its slots unused
+        const uint32_t per = 4 * g.n;
+        for (uint32_t i = tid; i < Q * per; i += NT) {
+            const uint32_t q = i / per, j = i % per, kq = grp * Q + q;
+            if (kq < n_keys)
+                s_cw[q * (CW_WORDS / 4) + j] = reinterpret_cast<const uint4 *>(keys + (size_t)kq * stride + 32)[j];
+        }
+    }
+    // the codewords of key q of the group
+    auto cw_of = [&](uint32_t q) {
+        if constexpr (CWL)
+            return CwLds{(lds_u8 *)(s_cw + q * (CW_WORDS / 4))};
+        else
+            return cw_global(KeyView{keys + (size_t)(grp * Q + q) * stride});
+    };
 
     PRF::fill(sm.tab, tid, NT);
 
@@ -363,7 +415,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
             ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == PRF::id) ? 1u + party : 0u;
             if (!ok)
-                atomicOr(&g_key_error, 1u);
+                atomicOr(status, PIR_STATUS_BAD_KEY);
             else
                 s = K.root();
         }
@@ -379,22 +431,20 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     if constexpr (PRF::QUAD) {
         const uint32_t qk = tid >> 2, w = tid & 3;
         if (tid < 4 * Q && sm.keyok[qk]) { // whole quads: qk is the same for the four lanes
-            const KeyView K{keys + (size_t)(grp * Q + qk) * stride};
+            const auto C = cw_of(qk);
             uint32_t s = sm.u.bfs[qk].w[w];
             for (uint32_t d = 1; d <= dtop; d++) {
                 const uint32_t c = (uint32_t)((g.row0 + row_base) >> (g.n - d)) & 1u;
                 const uint32_t t = quad_first(s) & 1u;
-                const uint32_t cw = *reinterpret_cast<const uint32_t *>(K.p + 32 + 64 * (size_t)(d - 1) + 32 * t +
-                                                                        16 * c + 4 * w);
-                s = P.quad_one(s, c, Qd) ^ cw;
+                s = P.quad_one(s, c, Qd) ^ C.word(d, t, c, w);
             }
             sm.u.bfs[qk].w[w] = s;
         }
     } else if (tid < Q && sm.keyok[tid]) {
-        const KeyView K{keys + (size_t)(grp * Q + tid) * stride};
+        const auto C = cw_of(tid);
         Seed s = sm.u.bfs[tid];
         for (uint32_t d = 1; d <= dtop; d++)
-            s = child_on_path(P, K, s, d, (uint32_t)((g.row0 + row_base) >> (g.n - d)) & 1u);
+            s = child_on_path(P, C, s, d, (uint32_t)((g.row0 + row_base) >> (g.n - d)) & 1u);
         sm.u.bfs[tid] = s;
     }
     __syncthreads();
@@ -409,15 +459,13 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
             const uint32_t q = nd >> (l - 1), j = nd & (half - 1);
             uint32_t c0 = 0, c1 = 0;
             if (mine && sm.keyok[q]) {
-                const KeyView K{keys + (size_t)(grp * Q + q) * stride};
+                const auto C = cw_of(q);
                 const uint32_t s = sm.u.bfs[nd].w[w];
                 const uint32_t t = quad_first(s) & 1u;
-                const uint32_t *cwp =
-                    reinterpret_cast<const uint32_t *>(K.p + 32 + 64 * (size_t)(dtop + l - 1) + 32 * t);
                 uint32_t a, b;
                 P.quad_pair(s, a, b, Qd);
-                c0 = a ^ cwp[w];
-                c1 = b ^ cwp[4 + w];
+                c0 = a ^ C.word(dtop + l, t, 0, w);
+                c1 = b ^ C.word(dtop + l, t, 1, w);
             }
             __syncthreads(); // every parent has been read
             if (mine) {
@@ -430,10 +478,8 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         const bool mine = tid < Q * half;
         const uint32_t q = tid >> (l - 1), j = tid & (half - 1);
         Seed c0{{0, 0, 0, 0}}, c1{{0, 0, 0, 0}};
-        if (mine && sm.keyok[q]) {
-            const KeyView K{keys + (size_t)(grp * Q + q) * stride};
-            children(P, K, sm.u.bfs[tid], dtop + l, c0, c1);
-        }
+        if (mine && sm.keyok[q])
+            children(P, cw_of(q), sm.u.bfs[tid], dtop + l, c0, c1);
         __syncthreads(); // every parent has been read
         if (mine) {
             sm.u.bfs[q * 2 * half + 2 * j] = c0;
@@ -453,7 +499,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     const uint32_t h = g.H - g.lgS;       // >= 1
     const uint32_t d0 = g.n - h;          // depth of the lane's root
     const uint32_t steps = 1u << (h - 1); // bottom nodes per lane
-    const KeyView K{keys + (size_t)(grp * Q + q) * stride};
+    const auto C = cw_of(q);
     Seed node = active ? sm.u.bfs[q * S_used + ln] : Seed{{0, 0, 0, 0}};
     const Seed root = node;
     Seed right[HMAX];
@@ -509,7 +555,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         if constexpr (MF) {
             const uint32_t *p0 = table + (mrow < rows ? mrow : rows - 1) * dim;
             const uint32_t *p1 = table + (mrow + 1 < rows ? mrow + 1 : rows - 1) * dim;
-            if (dim == 64) {
+            if (VEC4 && dim == 64) {
                 load_cols<4, true>(p0, dim, lane & 15, t0);
                 load_cols<4, true>(p1, dim, lane & 15, t1);
             } else {
@@ -533,14 +579,14 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         if (active) {
             for (uint32_t k = kst; k < h; k++) {
                 Seed c0, c1;
-                children(P, K, node, d0 + k, c0, c1);
+                children(P, C, node, d0 + k, c0, c1);
 #pragma unroll
                 for (int i = 1; i < HMAX; i++)
                     if ((uint32_t)i == k)
                         right[i] = c1;
                 node = c0;
             }
-            const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
+            const uint2 cw = C.cw_word0(g.n, node.w[0] & 1u);
             P.pair_word0(node.w, y0, y1);
             y0 ^= cw.x;
             y1 ^= cw.y;
@@ -727,6 +773,7 @@ constexpr int MAX_TASKS = 16;
 struct WaveTasks {
     WaveTask t[MAX_TASKS];
     uint32_t count, n_items;
+    uint32_t *status; // the call's status word
 };
 
 template <class PRF, int KT, bool VEC>
@@ -763,15 +810,18 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 
     const uint32_t q = lane & 15, sub = lane >> 4;
     const uint32_t kq = grp * 16 + q;
     const uint32_t h = g.h;
+    if (h == 0 || h > g.n || h > HMAX3)
+        return; // the planner keeps 1 <= h <= min(n, HMAX3); no barrier follows
 
     uint32_t ok = 0;
     const KeyView K{keys + (size_t)(kq < n_keys ? kq : 0) * key_step};
+    const CwGlobal C = cw_global(K);
     if (kq < n_keys) {
         const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
         const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
         ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == PRF::id) ? 1u + party : 0u;
         if (!ok && sub == 0)
-            atomicOr(&g_key_error, 1u);
+            atomicOr(tasks.status, PIR_STATUS_BAD_KEY);
     }
     const uint64_t lane_row0 = ((uint64_t)chunk * 4 + sub) << h;
     const bool active = ok && lane_row0 < rows;
@@ -781,7 +831,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 
     if (active) {
         node = K.root();
         for (uint32_t d = 1; d + h <= g.n; d++)
-            node = child_on_path(P, K, node, d, (uint32_t)((g.row0 + lane_row0) >> (g.n - d)) & 1u);
+            node = child_on_path(P, C, node, d, (uint32_t)((g.row0 + lane_row0) >> (g.n - d)) & 1u);
     }
     const uint32_t d0 = g.n - h;
     Seed right[HMAX3];
@@ -829,14 +879,14 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 
         if (active) {
             for (uint32_t k = __builtin_amdgcn_readfirstlane(kst); k < h; k++) {
                 Seed c0, c1;
-                children(P, K, node, d0 + k, c0, c1);
+                children(P, C, node, d0 + k, c0, c1);
 #pragma unroll
                 for (int i = 1; i < HMAX3; i++)
                     if ((uint32_t)i == k)
                         right[i] = c1;
                 node = c0;
             }
-            const uint2 cw = K.cw_word0(g.n, node.w[0] & 1u);
+            const uint2 cw = C.cw_word0(g.n, node.w[0] & 1u);
             P.pair_word0(node.w, y0, y1);
             y0 = r0 < rows ? y0 ^ cw.x : 0u; // rows past the table add nothing
             y1 = r0 + 1 < rows ? y1 ^ cw.y : 0u;

@@ -22,8 +22,11 @@ PRFS = {"aes128": PRF_AES128, "chacha20": PRF_CHACHA20}
 
 # the exported C ABI, as declared in include/pir.h
 EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_prf", "pir_answer_slice",
-           "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_plan", "pir_reconstruct",
+           "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_plan", "pir_plan_bins",
+           "pir_reconstruct", "pir_workspace_size", "pir_set_workspace", "pir_workspace_status",
            "pir_check_status", "pir_strerror", "pir_last_hip_error")
+WORKSPACE_BYTES = 256
+STATUS_BAD_KEY = 1
 KERNEL_WAVES, KERNEL_SMALL_BATCH = 1, 2
 BINS_MIN_LOG, BINS_MAX_DIM = 3, 128
 
@@ -99,6 +102,15 @@ def load(path: Path | None = None):
     lib.pir_plan.restype = ctypes.c_int
     lib.pir_plan.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32,
                              ctypes.POINTER(PirPlan)]
+    lib.pir_plan_bins.restype = ctypes.c_int
+    lib.pir_plan_bins.argtypes = [ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint32,
+                                  ctypes.c_uint32, ctypes.POINTER(PirPlan)]
+    lib.pir_workspace_size.restype = ctypes.c_size_t
+    lib.pir_workspace_size.argtypes = []
+    lib.pir_set_workspace.restype = ctypes.c_int
+    lib.pir_set_workspace.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
+    lib.pir_workspace_status.restype = ctypes.c_int
+    lib.pir_workspace_status.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
     lib.pir_reconstruct.restype = ctypes.c_int
     lib.pir_reconstruct.argtypes = [u32p, u32p, ctypes.c_uint32, u32p]
     lib.pir_check_status.restype = ctypes.c_int
@@ -285,6 +297,13 @@ def plan(n_keys: int, rows: int, dim: int, prf=PRF_AES128) -> dict:
     return {name: getattr(p, name) for name, _ in PirPlan._fields_}
 
 
+def plan_bins(rows: int, dim: int, n_clients: int, bin_log: int, prf=PRF_AES128) -> dict:
+    """The work plan pir_answer_bins uses for one table (no GPU needed)."""
+    p = PirPlan()
+    _check(load().pir_plan_bins(prf_id(prf), rows, dim, n_clients, bin_log, ctypes.byref(p)), "pir_plan_bins")
+    return {name: getattr(p, name) for name, _ in PirPlan._fields_}
+
+
 def n_bins(rows: int, bin_log: int) -> int:
     """Bins of 2^bin_log rows over a table of `rows` rows (the last may be shorter)."""
     return (int(rows) + (1 << bin_log) - 1) >> bin_log
@@ -345,5 +364,37 @@ def reconstruct(a0: np.ndarray, a1: np.ndarray) -> np.ndarray:
 
 
 def check_status() -> int:
-    """PIR_OK, or PIR_EKEY if a key with a bad header was seen (clears the flag)."""
+    """Status of the last call that used the library's own workspace on the
+    current device (after the caller has synchronised): PIR_OK, or PIR_EKEY if
+    it saw a key with a bad header."""
     return int(load().pir_check_status())
+
+
+def workspace(device=None):
+    """A status workspace (uint8 device tensor of pir_workspace_size() bytes)."""
+    import torch
+
+    return torch.zeros(int(load().pir_workspace_size()), dtype=torch.uint8,
+                       device=device if device is not None else "cuda")
+
+
+def set_workspace(ws) -> None:
+    """Bind `ws` (from workspace(), or None to unbind) as the status workspace
+    of the answer calls this thread makes from now on."""
+    import torch
+
+    lib = load()
+    if ws is None:
+        _check(lib.pir_set_workspace(None, 0), "pir_set_workspace")
+        return
+    _check_dev(ws, "workspace", (torch.uint8,))
+    _check(lib.pir_set_workspace(ws.data_ptr(), ws.numel()), "pir_set_workspace")
+
+
+def workspace_status(ws, stream=None) -> int:
+    """Status of the last call that used workspace `ws`, read in the order of
+    `stream` (waits for the calls enqueued on it): PIR_OK or PIR_EKEY."""
+    import torch
+
+    _check_dev(ws, "workspace", (torch.uint8,))
+    return int(load().pir_workspace_status(ws.data_ptr(), _stream_handle(stream)))

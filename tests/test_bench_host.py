@@ -140,3 +140,28 @@ def test_every_stored_counter_summary_names_its_workload():
         assert t["prf"] == prf and t["bytes_per_launch"] > 0
         assert f"{keys} keys, 2^{log_rows} x {dim} table" in t["note"], path
         assert (f"--dim {dim} " in t["command"]) == (dim != 64), path
+
+
+def test_roofline_binds_on_lds_lookups_for_aes_and_the_valu_for_chacha():
+    """AES-128 is bound by LDS table lookups: frac = algorithmic lookups per
+    launch / launch time / the unit-count LDS peak; ChaCha20 has no table and
+    is bound by the VALU."""
+    kern_s = 0.021
+    r, lds, valu = bench.rooflines("aes128", 20, 1024, 64, kern_s, "k_pir_waves")
+    lookups = 360_776_896_512
+    assert r["bound"] == "lds" and r["unit"] == "T lookups/s" and r["kernel"] == "k_pir_waves"
+    assert r["lookups_per_launch"] == lookups == lds["lookups_per_launch"]
+    assert abs(r["frac"] - lookups / kern_s / bench.PEAK_LDS_LOOKUPS) < 1e-4
+    assert abs(r["peak"] - 19.661) < 1e-3 and r["frac"] == lds["frac"]
+    assert abs(valu["frac"] - 686_120_343_552 / kern_s / bench.PEAK_INT32_OPS) < 1e-4
+    r, lds, valu = bench.rooflines("chacha20", 20, 1024, 64, kern_s, "k_pir_waves")
+    assert lds is None and r["bound"] == "alu" and r["frac"] == valu["frac"]
+    assert r["valu_ops_per_launch"] == 1_021_127_478_272
+
+
+def test_host_cpus_reports_what_the_oracle_runs_on():
+    h = bench.host_cpus()
+    assert 1 <= h["usable_cores"] <= h["nproc"] <= (h["os_cpu_count"] or h["nproc"])
+    if h["cgroup_cpu_quota"]:
+        assert h["usable_cores"] <= h["cgroup_cpu_quota"]
+    assert h["cpu_model"] is None or isinstance(h["cpu_model"], str)

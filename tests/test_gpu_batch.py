@@ -56,6 +56,8 @@ CASES = [
     (1 << 14, 64, 12, 16), (777, 3, 3, 2), (1 << 13, 33, 13, 20),
     # rows of 65..128 words (eight column tiles per lane)
     (1 << 12, 128, 9, 6), (3000, 100, 7, 17), (2000, 65, 11, 3),
+    # tables of 1..4 rows: a single bin shorter than any wave item's subtrees
+    (1, 16, 3, 3), (2, 64, 3, 2), (3, 5, 4, 17), (4, 128, 3, 1), (4, 32, 12, 16),
 ]
 
 
@@ -200,3 +202,24 @@ def test_bins_bad_key_header(O, pirmod):
         c, b = divmod(i, nb)
         want = O.answer(K0[i], T[b << bin_log:(b + 1) << bin_log])
         assert (flat[i] == want).all(), i
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+def test_bins_tiny_tables_beside_a_large_one(O, pirmod, prf):
+    """Tables of 1..4 rows share one wave launch with larger tables of the same
+    row width (the multi-table plan gives every table its own subtree height):
+    every per-server answer bit-exact, every reconstruction T[b I + alpha]."""
+    specs = [(3, 16, 3, 5), (1 << 12, 16, 9, 20), (1, 16, 4, 2), (4, 16, 3, 17), (2, 16, 5, 1)]
+    tabs, keysets, want, alphas_l = [], [], [], []
+    for i, (rows, dim, bin_log, clients) in enumerate(specs):
+        seed = 500 + 10 * i + prf
+        T = W.make_table(rows, dim, seed).numpy().view(np.uint32)
+        alphas = random_alphas(rows, bin_log, clients, seed)
+        K0, _ = oracle_bin_keys(O, alphas, bin_log, seed, prf)
+        tabs.append(T)
+        keysets.append(K0)
+        alphas_l.append(alphas)
+        want.append(O.answer_bins(K0, T, bin_log, clients, nthreads=cpu_threads()))
+    got = run_bins(pirmod, tabs, keysets, [s[3] for s in specs], [s[2] for s in specs], prf)
+    for i in range(len(specs)):
+        assert (got[i] == want[i]).all(), specs[i]

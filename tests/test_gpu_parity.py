@@ -135,13 +135,16 @@ def test_bad_key_header_gives_zero_row(O, pirmod):
     keys = np.concatenate([K0, K1])
     keys[1, 0] = 7          # bad version
     keys[2, 2] = 11         # wrong domain size
+    good = gpu_answer(pirmod, keys[[0, 3]], T.cuda())
     assert pirmod.check_status() == pirmod.PIR_OK
     got = gpu_answer(pirmod, keys, T.cuda())
     assert pirmod.check_status() == pirmod.PIR_EKEY
-    assert pirmod.check_status() == pirmod.PIR_OK  # flag cleared
+    assert pirmod.check_status() == pirmod.PIR_EKEY  # reading leaves the call's status
     assert (got[1] == 0).all() and (got[2] == 0).all()
     want = O.answer_batch(keys[[0, 3]], T.numpy().view(np.uint32), nthreads=2)
-    assert (got[[0, 3]] == want).all()
+    assert (got[[0, 3]] == want).all() and (good == want).all()
+    gpu_answer(pirmod, keys[[0, 3]], T.cuda())
+    assert pirmod.check_status() == pirmod.PIR_OK  # the next call reports its own status
 
 
 def test_repeat_launches_identical(O, pirmod):
@@ -711,3 +714,39 @@ def test_random_shapes_against_the_oracle(O, pirmod):
         assert (out.cpu().numpy().view(np.uint32) == want).all(), (case, rows, dim, nkeys, prf, p)
     assert {(pirmod.KERNEL_WAVES, False), (pirmod.KERNEL_SMALL_BATCH, False)} <= seen, seen
     assert any(tail for _, tail in seen), seen
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+@pytest.mark.parametrize("rows,dim,nkeys", [
+    (1 << 12, 64, 64),    # wave kernel, vector loads of 16 bytes when aligned
+    (1 << 12, 32, 64),    # wave kernel, 8-byte loads when aligned
+    (1 << 12, 16, 64),    # wave kernel, 16 columns
+    (1 << 14, 64, 3),     # small-batch kernel (16-byte row segments when aligned)
+    (1 << 14, 64, 16),    # small-batch kernel, matrix-core product over 16 keys
+    (1 << 12, 100, 40),   # eight column tiles
+])
+def test_table_at_a_4_byte_offset(O, pirmod, prf, rows, dim, nkeys):
+    """A table whose base is 4-byte but not 16-byte aligned (a contiguous view
+    one word into a buffer) is read with single-word loads and answers exactly
+    as an aligned copy does."""
+    import torch
+
+    seed = rows + dim + nkeys + prf
+    T = W.make_table(rows, dim, seed)
+    buf = torch.empty(rows * dim + 4, dtype=torch.int32, device="cuda")
+    buf[1:1 + rows * dim].copy_(T.reshape(-1).cuda())
+    Tview = buf[1:1 + rows * dim].view(rows, dim)
+    assert Tview.data_ptr() % 16 == 4 and Tview.is_contiguous()
+    a = W.uniform_indices(rows, nkeys, seed)
+    K0, _ = O.gen_batch(log_domain(rows), a, W.key_seeds(nkeys, seed), prf_id=prf)
+    keys = torch.from_numpy(K0).cuda()
+    got = pirmod.answer(keys, Tview, prf=prf)
+    torch.cuda.synchronize()
+    want = O.answer_batch(K0, T.numpy().view(np.uint32), nthreads=cpu_threads())
+    assert (got.cpu().numpy().view(np.uint32) == want).all()
+    # the same table, aligned, in a multi-table call beside the offset one
+    Ta = T.cuda()
+    out, views = pirmod.answer_multi([Tview, Ta], [nkeys, nkeys], torch.cat([keys, keys]), prf=prf)
+    torch.cuda.synchronize()
+    for v in views:
+        assert (v.cpu().numpy().view(np.uint32) == want).all()

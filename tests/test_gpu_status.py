@@ -1,0 +1,177 @@
+"""Per-call status in a caller's workspace (include/pir.h: pir_set_workspace,
+pir_workspace_status), on the GPU.
+
+Each answer call clears its status word with its first kernel and sets
+PIR_STATUS_BAD_KEY there for a key with a bad header; the word is the one of
+the workspace bound by the calling thread.  Two streams with a workspace
+each report independently; a call that is split over several launches (a
+remainder past whole groups of 16 keys, several tables) reports once; a
+captured graph reports the status of each replay.  Outputs are checked
+against the oracle as everywhere else.
+"""
+import numpy as np
+import pytest
+
+from conftest import cpu_threads
+from paper_2301_10904_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def pirmod(gpu_lib):
+    from paper_2301_10904_amd import pir
+
+    yield pir
+    pir.set_workspace(None)
+
+
+def keyset(O, rows, count, seed, prf=0):
+    n = max(1, (rows - 1).bit_length())
+    a = W.uniform_indices(rows, count, seed)
+    K0, _ = O.gen_batch(n, a, W.key_seeds(count, seed), prf_id=prf)
+    return K0
+
+
+def test_two_streams_each_with_its_own_workspace(O, pirmod):
+    import torch
+
+    rows, dim = 1 << 12, 64
+    T = W.make_table(rows, dim, 31)
+    Tn, Td = T.numpy().view(np.uint32), T.cuda()
+    good = keyset(O, rows, 40, 31)
+    bad = good.copy()
+    bad[7, 1] = 2  # party 2 does not exist
+    want = O.answer_batch(good, Tn, nthreads=cpu_threads())
+    streams = (torch.cuda.Stream(), torch.cuda.Stream())
+    spaces = (pirmod.workspace(), pirmod.workspace())
+    kd = {"good": torch.from_numpy(good).cuda(), "bad": torch.from_numpy(bad).cuda()}
+    torch.cuda.synchronize()
+    for which in (("good", "bad"), ("bad", "good"), ("bad", "bad"), ("good", "good")):
+        outs = []
+        for st, ws, w in zip(streams, spaces, which):
+            with torch.cuda.stream(st):
+                pirmod.set_workspace(ws)
+                outs.append(pirmod.answer(kd[w], Td, prf=0))
+        pirmod.set_workspace(None)
+        for st, ws, w in zip(streams, spaces, which):
+            assert pirmod.workspace_status(ws, st) == (pirmod.PIR_EKEY if w == "bad" else pirmod.PIR_OK), which
+        torch.cuda.synchronize()
+        for o, w in zip(outs, which):
+            g = o.cpu().numpy().view(np.uint32)
+            if w == "good":
+                assert (g == want).all()
+            else:
+                assert (g[7] == 0).all() and (np.delete(g, 7, 0) == np.delete(want, 7, 0)).all()
+
+
+def test_each_call_reports_its_own_status(O, pirmod):
+    """A call after a bad one starts from a clear word; the library's own
+    workspace is untouched by calls that use a bound one."""
+    import torch
+
+    rows, dim = 3000, 16
+    Td = W.make_table(rows, dim, 32).cuda()
+    good = keyset(O, rows, 5, 32)
+    bad = good.copy()
+    bad[0, 3] = 9  # unknown PRF id
+    ws = pirmod.workspace()
+    pirmod.set_workspace(ws)
+    try:
+        pirmod.answer(torch.from_numpy(bad).cuda(), Td)
+        assert pirmod.workspace_status(ws) == pirmod.PIR_EKEY
+        pirmod.answer(torch.from_numpy(good).cuda(), Td)
+        assert pirmod.workspace_status(ws) == pirmod.PIR_OK
+        pirmod.answer(torch.from_numpy(bad).cuda(), Td)
+    finally:
+        pirmod.set_workspace(None)
+    pirmod.answer(torch.from_numpy(good).cuda(), Td)
+    torch.cuda.synchronize()
+    assert pirmod.check_status() == pirmod.PIR_OK        # the library's own word
+    assert pirmod.workspace_status(ws) == pirmod.PIR_EKEY  # the bound one kept its last call's status
+
+
+@pytest.mark.parametrize("where", ["head", "tail"])
+def test_a_split_call_reports_once(O, pirmod, where):
+    """17 keys on 2^20 rows run as a launch over 16 keys and a second launch
+    over the last one (pir_plan tail_keys = 1); a bad key in either launch is
+    reported, because only the call's first launch clears the word."""
+    import torch
+
+    rows, dim = 1 << 20, 16
+    assert pirmod.plan(17, rows, dim)["tail_keys"] == 1
+    Td = W.make_table(rows, dim, 33, device="cuda")
+    keys = keyset(O, rows, 17, 33)
+    keys[3 if where == "head" else 16, 0] = 2  # bad version
+    ws = pirmod.workspace()
+    pirmod.set_workspace(ws)
+    try:
+        out = pirmod.answer(torch.from_numpy(keys).cuda(), Td)
+        assert pirmod.workspace_status(ws) == pirmod.PIR_EKEY
+    finally:
+        pirmod.set_workspace(None)
+    got = out.cpu().numpy().view(np.uint32)
+    bad = 3 if where == "head" else 16
+    assert (got[bad] == 0).all()
+    other = (bad + 1) % 17
+    assert (got[other] == O.answer(keys[other], Td.cpu().numpy().view(np.uint32))).all()
+
+
+def test_status_of_each_graph_replay(O, pirmod):
+    import torch
+
+    rows, dim = 5000, 32
+    T = W.make_table(rows, dim, 34)
+    Tn, Td = T.numpy().view(np.uint32), T.cuda()
+    good = keyset(O, rows, 20, 34)
+    bad = good.copy()
+    bad[19, 2] = 12  # wrong domain
+    keys = torch.from_numpy(good).cuda()
+    out = torch.empty((20, dim), dtype=torch.int32, device="cuda")
+    ws = pirmod.workspace()
+    pirmod.set_workspace(ws)
+    try:
+        pirmod.answer(keys, Td, out)  # eager, before capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            pirmod.answer(keys, Td, out)
+    finally:
+        pirmod.set_workspace(None)
+    torch.cuda.synchronize()
+    want = O.answer_batch(good, Tn, nthreads=cpu_threads())
+    for rep, ks in enumerate([bad, good, bad, bad, good]):
+        keys.copy_(torch.from_numpy(ks).cuda())
+        g.replay()
+        torch.cuda.synchronize()
+        st = pirmod.workspace_status(ws)
+        assert st == (pirmod.PIR_EKEY if ks is bad else pirmod.PIR_OK), rep
+        got = out.cpu().numpy().view(np.uint32)
+        if ks is bad:
+            assert (got[19] == 0).all() and (got[:19] == want[:19]).all()
+        else:
+            assert (got == want).all()
+
+
+def test_multi_table_call_reports_once(O, pirmod):
+    import torch
+
+    specs = [(1 << 12, 32, 40), (1 << 10, 32, 3), (5000, 64, 20)]
+    tabs, keysets = [], []
+    for i, (rows, dim, cnt) in enumerate(specs):
+        tabs.append(W.make_table(rows, dim, 40 + i).cuda())
+        keysets.append(keyset(O, rows, cnt, 40 + i))
+    stride = max(k.shape[1] for k in keysets)
+    keys = np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keysets])
+    ws = pirmod.workspace()
+    pirmod.set_workspace(ws)
+    try:
+        for bad_at in (None, 0, 41, 60):
+            ks = keys.copy()
+            if bad_at is not None:
+                ks[bad_at, 0] = 3
+            pirmod.answer_multi(tabs, [s[2] for s in specs], torch.from_numpy(ks).cuda())
+            want = pirmod.PIR_OK if bad_at is None else pirmod.PIR_EKEY
+            assert pirmod.workspace_status(ws) == want, bad_at
+    finally:
+        pirmod.set_workspace(None)

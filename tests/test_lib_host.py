@@ -421,3 +421,67 @@ def test_too_much_work_is_refused_before_any_launch(lib):
     fake = ctypes.c_void_p(0x100000)
     assert lib.pir_answer(fake, 16384, stride, fake, 1 << 32, 1, fake, None) == pir.PIR_ENOMEM
     assert lib.pir_answer_prf(1, fake, 16384, stride, fake, 1 << 32, 1, fake, None) == pir.PIR_ENOMEM
+
+
+def test_workspace_api_without_gpu(lib):
+    """The status workspace: its size, and the binding rules (checked on the
+    host; a bound workspace is only dereferenced by kernels)."""
+    assert lib.pir_workspace_size() == pir.WORKSPACE_BYTES == 256
+    fake = ctypes.c_void_p(0x10000)
+    assert lib.pir_set_workspace(fake, 255) == pir.PIR_EINVAL                  # too short
+    assert lib.pir_set_workspace(ctypes.c_void_p(0x10008), 256) == pir.PIR_EINVAL  # not 16-byte aligned
+    assert lib.pir_set_workspace(fake, 256) == pir.PIR_OK
+    assert lib.pir_set_workspace(fake, 4096) == pir.PIR_OK
+    assert lib.pir_set_workspace(None, 0) == pir.PIR_OK                        # unbind
+    assert lib.pir_workspace_status(None, None) == pir.PIR_EINVAL
+    assert lib.pir_workspace_status(ctypes.c_void_p(0x10004), None) == pir.PIR_EINVAL
+    # argument errors are still found before any device work, with or without a binding
+    assert lib.pir_set_workspace(fake, 256) == pir.PIR_OK
+    ks = pir.key_size(10)
+    assert lib.pir_answer(fake, 1, ks, fake, 1024, 0, fake, None) == pir.PIR_EINVAL
+    assert lib.pir_set_workspace(None, 0) == pir.PIR_OK
+
+
+def test_workspace_binding_is_per_thread(lib):
+    """A binding made by one thread does not change another's: a short buffer
+    is rejected in every thread, and each thread's unbind leaves the others."""
+    import threading
+
+    res = {}
+
+    def worker(i):
+        res[i] = (lib.pir_set_workspace(ctypes.c_void_p(0x20000 + 256 * i), 256),
+                  lib.pir_set_workspace(ctypes.c_void_p(0x20000), 16),
+                  lib.pir_set_workspace(None, 0))
+
+    ts = [threading.Thread(target=worker, args=(i,)) for i in range(4)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert all(r == (pir.PIR_OK, pir.PIR_EINVAL, pir.PIR_OK) for r in res.values())
+
+
+@pytest.mark.parametrize("rows", [1, 2, 3, 4, 5, 8, 9, 777, 1 << 14])
+@pytest.mark.parametrize("bin_log", [3, 4, 10, 32])
+def test_plan_bins_subtree_height_stays_in_the_bin(rows, bin_log):
+    """Partial batch retrieval plans: the per-lane subtree height h satisfies
+    1 <= h <= bin_log and never exceeds the aligned subtree holding a bin's rows
+    (tables of 1..4 rows included), and the items cover every bin."""
+    for prf in ("aes128", "chacha20"):
+        for clients in (1, 16, 17):
+            p = pir.plan_bins(rows, 16, clients, bin_log, prf=prf)
+            bin_rows = min(rows, 1 << bin_log)
+            m = max(1, (bin_rows - 1).bit_length())
+            assert p["kernel"] == pir.KERNEL_WAVES and p["n"] == bin_log
+            assert 1 <= p["subtree_log"] <= min(m, bin_log, 9), p
+            assert p["descent_levels"] == bin_log - p["subtree_log"]
+            assert p["rows_per_item"] == 4 << p["subtree_log"]
+            chunks = -(-bin_rows // p["rows_per_item"])
+            assert p["items"] == pir.n_bins(rows, bin_log) * chunks * (-(-clients // 16))
+
+
+def test_plan_bins_rejects_what_answer_bins_rejects():
+    for args in [(1 << 10, 129, 1, 5), (1 << 10, 16, 1, 2), (0, 16, 1, 5), (1 << 10, 16, 0, 5), (1 << 10, 16, 1, 33)]:
+        with pytest.raises(pir.PirError):
+            pir.plan_bins(*args)
