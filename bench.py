@@ -152,10 +152,42 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), p))
 
 
-def cpu_baseline(keys_np, table_np, sample_keys: int, threads: int):
-    """The oracle (untuned) on a bounded sample of the same workload."""
+def host_cpus() -> dict:
+    """The host's CPU: model, `nproc`-style counts and the cores this process
+    may use (its affinity set, further limited by a cgroup CPU quota if one is
+    set): the oracle runs one thread per usable core."""
+    info = {"cpu_model": None, "os_cpu_count": os.cpu_count()}
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                info["cpu_model"] = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count() or 1
+    info["nproc"] = usable  # what `nproc` prints: the affinity set
+    quota = None
+    try:
+        q, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if q != "max":
+            quota = max(1, int(int(q) / int(period)))
+    except (OSError, ValueError):
+        pass
+    info["cgroup_cpu_quota"] = quota
+    info["usable_cores"] = min(usable, quota) if quota else usable
+    return info
+
+
+def cpu_baseline(keys_np, table_np, sample_keys: int, shape: str):
+    """The oracle (untuned) on a bounded sample of the same workload, one key
+    per thread on every usable host core."""
     import oracle
 
+    host = host_cpus()
+    threads = host["usable_cores"]
     O = oracle.Oracle()
     sub = keys_np[:sample_keys]
     t0 = time.perf_counter()
@@ -163,8 +195,10 @@ def cpu_baseline(keys_np, table_np, sample_keys: int, threads: int):
     dt = time.perf_counter() - t0
     return {"value": sample_keys / dt, "unit": "server queries/s", "cores": threads,
             "kind": "oracle",
-            "sample": f"{sample_keys} keys of the same workload (2^20 rows x 64 uint32), "
-                      f"one key per thread, {dt:.1f} s"}
+            "sample": f"{sample_keys} keys of the same workload ({shape}), "
+                      f"one key per thread, {dt:.1f} s",
+            "nproc": host["nproc"], "os_cpu_count": host["os_cpu_count"],
+            "cgroup_cpu_quota": host["cgroup_cpu_quota"], "cpu_model": host["cpu_model"]}
 
 
 def main():
@@ -182,6 +216,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="keys of the workload the oracle answers for the CPU baseline (x8 for ChaCha20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--large-keys", type=int, default=2048, metavar="PAIRS",
+                    help="key pairs per launch of the 2^25 x 64 record in the default line (0: omit it)")
+    ap.add_argument("--large-steps", type=int, default=3,
+                    help="timed launches of the 2^25 x 64 record (after one warm-up)")
     ap.add_argument("--no-prf-ceiling", dest="prf_ceiling", action="store_false",
                     help="skip the PRF-engine ceiling (libpir_engine.so) in the default line")
     ap.add_argument("--no-peaks", dest="peaks", action="store_false",
@@ -303,14 +341,10 @@ def main():
 
     calibration_copy(args.calibrate_copy, dev)
 
-    valu_ops, lookups = algorithmic_work(n, B, dim, prf=prf)
     kern_s = float(np.mean(launch_ms)) / 1e3
-    achieved = valu_ops / kern_s / 1e12
-    peak = PEAK_INT32_OPS / 1e12
-    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-                "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": measured_traffic(prf, n, B, dim),
-                "kernel": "k_pir_waves", "valu_ops_per_launch": valu_ops,
-                "avg_launch_ms": round(kern_s * 1e3, 4), "kernel_digest": kernel_digest()}
+    plan = pir.plan(B, rows, dim, prf=prf)
+    kernel = KERNEL_NAMES[plan["kernel"]]
+    roofline, roofline_lds, roofline_valu = rooflines(prf, n, B, dim, kern_s, kernel)
     # the fused kernel's tree nodes per second against the PRF engine alone
     # (the same node mix, tables and workgroups, nothing else), and the
     # contraction's multiply-adds per second
@@ -318,23 +352,23 @@ def main():
     prf_ceiling = prf_engine_rate(prf, nodes / kern_s) if args.prf_ceiling else None
     contraction = {"macs_per_s": round(B * rows * dim / kern_s, 1), "unit": "uint32 MAC/s",
                    "note": "int8 matrix cores on balanced base-256 digits, exact mod 2^32"}
-    lds_rate = lookups / kern_s / 1e12
-    roofline_lds = {"achieved": round(lds_rate, 3), "peak": round(PEAK_LDS_LOOKUPS / 1e12, 3),
-                    "unit": "T lookups/s", "frac": round(lds_rate * 1e12 / PEAK_LDS_LOOKUPS, 4),
-                    "lookups_per_launch": lookups} if lookups else None
     # the same rates against what the probes measure on this GPU (the
-    # published peaks above stay the roofline's denominators)
+    # published or unit-count peaks above stay the roofline's denominators)
     peaks = measured_peaks() if args.peaks else None
     if peaks:
-        roofline["frac_of_measured"] = round(achieved / peaks["valu_T_lane_ops"], 4)
+        roofline_valu["frac_of_measured"] = round(roofline_valu["achieved"] / peaks["valu_T_lane_ops"], 4)
         if roofline_lds:
-            roofline_lds["frac_of_measured"] = round(lds_rate / peaks["lds_T_lookups"], 4)
+            roofline_lds["frac_of_measured"] = round(roofline_lds["achieved"] / peaks["lds_T_lookups"], 4)
+        roofline["frac_of_measured"] = (roofline_lds or roofline_valu)["frac_of_measured"]
+
+    # config 4 beside the default line: the 8 GiB table, its largest batch
+    large = large_batch_record(prf, args.large_keys, args.large_steps) if args.large_keys else None
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = max(1, min(16, os.cpu_count() or 1))
         cpu = cpu_baseline(keys_np, table.cpu().numpy().view(np.uint32),
-                           args.cpu_sample * (8 if prf == "chacha20" else 1), threads)
+                           args.cpu_sample * (8 if prf == "chacha20" else 1),
+                           f"2^{args.log_rows} rows x {dim} uint32")
 
     res = {
         "metric": METRIC,
@@ -365,14 +399,89 @@ def main():
         "exact": recon_ok,
         "roofline": roofline,
         "roofline_lds": roofline_lds,
+        "roofline_valu": roofline_valu,
         "prf_ceiling": prf_ceiling,
         "contraction": contraction,
         "measured_peaks": peaks,
         "cpu_baseline": cpu,
+        "large_table": large,
     }
     print(json.dumps(res), flush=True)
-    if not recon_ok:
+    if not recon_ok or (large and not large["exact"]):
         sys.exit(1)
+
+
+KERNEL_NAMES = {1: "k_pir_waves", 2: "k_pir_fused"}
+
+
+def rooflines(prf: str, n: int, keys: int, dim: int, kern_s: float, kernel: str):
+    """(roofline, roofline_lds, roofline_valu) of a launch of `keys` keys over
+    2^n rows that took kern_s seconds.  The binding unit: LDS table lookups
+    for AES-128 (every S-box and T-table read is one ds_read_b32, and the VALU
+    work overlaps them), the VALU for the table-free ChaCha20."""
+    valu_ops, lookups = algorithmic_work(n, keys, dim, prf=prf)
+    valu_rate = valu_ops / kern_s / 1e12
+    lds_rate = lookups / kern_s / 1e12
+    roofline_valu = {"achieved": round(valu_rate, 3), "peak": round(PEAK_INT32_OPS / 1e12, 3), "unit": "TOP/s",
+                     "frac": round(valu_rate * 1e12 / PEAK_INT32_OPS, 4), "valu_ops_per_launch": valu_ops}
+    roofline_lds = {"achieved": round(lds_rate, 3), "peak": round(PEAK_LDS_LOOKUPS / 1e12, 3),
+                    "unit": "T lookups/s", "frac": round(lds_rate * 1e12 / PEAK_LDS_LOOKUPS, 4),
+                    "lookups_per_launch": lookups} if lookups else None
+    common = {"traffic": measured_traffic(prf, n, keys, dim), "kernel": kernel,
+              "avg_launch_ms": round(kern_s * 1e3, 4), "kernel_digest": kernel_digest()}
+    head = ("achieved", "peak", "unit", "frac")
+    if roofline_lds:
+        roofline = {"bound": "lds", **{k: roofline_lds[k] for k in head}, **common, "lookups_per_launch": lookups}
+    else:
+        roofline = {"bound": "alu", **{k: roofline_valu[k] for k in head}, **common, "valu_ops_per_launch": valu_ops}
+    return roofline, roofline_lds, roofline_valu
+
+
+def large_batch_record(prf: str, pairs: int, steps: int) -> dict:
+    """The 2^25 x 64 table (8 GiB, resident) with 2 pairs keys per launch:
+    one warm-up and `steps` timed launches (HIP events on the launch stream),
+    every reconstruction checked against T[alpha], plus the single key on the
+    same table (HBM-bound: the table streamed once)."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    rows, dim, seed, n = 1 << 25, 64, 4, 25
+    T = W.make_table(rows, dim, seed, device=dev)
+    a = W.uniform_indices(rows, pairs, seed)
+    K0, K1 = pir.gen_batch(n, a, W.key_seeds(pairs, seed), prf=prf)
+    keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
+    B = 2 * pairs
+    out = torch.empty((B, dim), dtype=torch.int32, device=dev)
+    sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=prf), steps, 1)
+    got = out.cpu().numpy().view(np.uint32)
+    recon = ((got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF).astype(np.uint32)
+    exact = bool((recon == W.table_rows_np(a, dim, seed)).all())
+    _, lookups = algorithmic_work(n, B, dim, prf=prf)
+    kern_s = float(np.mean(ms)) / 1e3
+    k1 = keys[:1].contiguous()
+    o1 = torch.empty((1, dim), dtype=torch.int32, device=dev)
+    _, ms1 = time_launches(lambda: pir.answer(k1, T, o1, prf=prf), 50, 3)
+    p50 = percentile(ms1, 50)
+    gbs = rows * dim * 4 / (p50 * 1e-3) / 1e9
+    del T, keys, out
+    torch.cuda.empty_cache()
+    rec = {"workload": f"one table 2^25 rows x 64 uint32 (8 GiB) resident in HBM, {pairs} key pairs = {B} keys "
+                       f"per launch, uniform alpha, {'AES-128' if prf == 'aes128' else 'ChaCha20'} PRF",
+           "keys_per_launch": B, "warmup": 1, "steps": steps, "server_qps": round(B / sec, 1),
+           "ms_per_launch": [round(x, 2) for x in ms], "exact": exact,
+           "kernel": KERNEL_NAMES[pir.plan(B, rows, dim, prf=prf)["kernel"]],
+           "single_query": {"p50_ms": round(p50, 4), "p99_ms": round(percentile(ms1, 99), 4), "samples": len(ms1),
+                            "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
+                                         "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}}}
+    if lookups:
+        rate = lookups / kern_s
+        rec["roofline"] = {"bound": "lds", "achieved": round(rate / 1e12, 3),
+                           "peak": round(PEAK_LDS_LOOKUPS / 1e12, 3), "unit": "T lookups/s",
+                           "frac": round(rate / PEAK_LDS_LOOKUPS, 4)}
+    return rec
 
 
 def engine_lib(what: str):
