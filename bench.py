@@ -87,8 +87,8 @@ def algorithmic_work(n: int, keys: int, dim: int, valu_product: bool = False, pr
 
 
 def kernel_digest() -> str:
-    """Fingerprint of the kernel sources' code: comments and whitespace are
-    dropped, so editing a comment keeps the stored counters valid."""
+    """Fingerprint of the kernel sources' code (comments and whitespace are
+    dropped, so editing a comment keeps the stored counters valid)."""
     import hashlib
     import re
 

@@ -229,10 +229,56 @@ typedef struct {
     uint32_t descent_levels;      /* tree levels walked from the root to an item's subtree */
     uint32_t bfs_levels;          /* breadth-first levels in LDS (small-batch kernel) */
     uint32_t tail_keys;           /* the last tail_keys keys (1..8 past whole groups of 16) go to a
-                                     second launch on the small-batch kernel; the fields above
-                                     describe the first launch, over the other keys */
+                                     second launch, planned as a batch of their own; the fields
+                                     above describe the first launch, over the other keys */
+    uint32_t source;              /* PIR_PLAN_MODEL or PIR_PLAN_TUNED: where the first launch's
+                                     plan came from */
 } pir_plan_t;
+#define PIR_PLAN_MODEL 0 /* the library's cost model and measured thresholds */
+#define PIR_PLAN_TUNED 1 /* an entry of the tuned plan table (pir_set_tuning) */
 int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_plan_t *out);
+
+/* Tuned plans (sections 3.2.1 and 3.2.5 tune the batch scheduling, and
+ * section 3.2.3 its node budget K, by measurement; here the project's
+ * autotuner, paper_2301_10904_amd/autotune.py, times the candidate plans of
+ * each shape on the GPU and hands the winners to the library).  An entry
+ * covers single-table calls (pir_answer, pir_answer_prf, pir_answer_slice)
+ * of one PRF whose rows lie in an aligned subtree of height n, with row
+ * widths dim_lo..dim_hi and batches of keys_lo..keys_hi keys; the first
+ * matching entry fixes the fields it sets, the model the rest.  Multi-table
+ * and bins calls always use the model.  A field value the call cannot use
+ * (the wave kernel on rows wider than 128 words, 16 keys per workgroup on
+ * rows of 65..128 words, a height above what the rows allow) falls back to
+ * the model or is clamped, so any entry gives correct answers. */
+#define PIR_TUNE_MODEL 0xffffffffu /* tail_keys: keep the model's rule */
+typedef struct {
+    uint32_t prf_id;             /* PIR_PRF_* */
+    uint32_t n;                  /* 1..32 */
+    uint32_t dim_lo, dim_hi;     /* 1 <= dim_lo <= dim_hi <= PIR_MAX_DIM */
+    uint32_t keys_lo, keys_hi;   /* 1 <= keys_lo <= keys_hi */
+    uint32_t kernel;             /* 0 (the model's), PIR_KERNEL_WAVES or PIR_KERNEL_SMALL_BATCH */
+    uint32_t subtree_log;        /* wave kernel: 0 (the model's) or 1..9 */
+    uint32_t keys_per_item;      /* small-batch kernel: 0 (the model's), 1, 2, 4, 8 or 16 */
+    uint32_t tail_keys;          /* PIR_TUNE_MODEL, 0 (never split off a remainder) or 1..8: a
+                                    remainder of 1..tail_keys keys past whole groups of 16 gets
+                                    a launch of its own */
+} pir_tune_t;
+#define PIR_TUNE_MAX_ENTRIES 65536
+
+/* Replaces the tuned plan table with a copy of entries[0..count); count = 0
+ * clears it (every plan from the model).  Process-wide; calls already
+ * enqueued are unaffected, and calls planned concurrently see either table.
+ * PIR_EINVAL (the table unchanged) for a null pointer with count > 0, more
+ * than PIR_TUNE_MAX_ENTRIES entries, or an entry outside the ranges above. */
+int pir_set_tuning(const pir_tune_t *entries, uint32_t count);
+
+/* Entries of the tuned plan table. */
+uint32_t pir_tuning_count(void);
+
+/* Static, NUL-terminated fingerprint of the kernel sources this library was
+ * built from (comments and layout ignored): a tuned plan table is only valid
+ * for the kernels it was measured on. */
+const char *pir_kernel_digest(void);
 
 /* The work plan pir_answer_bins would use for a call over this one table
  * (section 4.1: n_clients clients, one key per bin of 2^bin_log rows), for

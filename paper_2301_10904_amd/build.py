@@ -14,6 +14,27 @@ SOURCES = ["pir_device.hip", "pir_host.cpp"]
 ENGINE_LIB = PKG / "libpir_engine.so"
 ENGINE_SOURCES = ["prf_engine.hip", "peak_probes.hip"]
 
+# the sources of the kernels' device code: their fingerprint is compiled into
+# the library (pir_kernel_digest) and keys measurements taken on it
+KERNEL_SOURCES = ["pir_kernels.h", "aes_gfx950.h", "aes_tables.h", "chacha_gfx950.h", "quad_gfx950.h"]
+
+
+def kernel_digest() -> str:
+    """Fingerprint of the kernel sources' code: comments and whitespace are
+    dropped, so editing a comment keeps measurements taken on the kernels
+    valid."""
+    import hashlib
+    import re
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        text = (CSRC / f).read_text()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        h.update(" ".join(text.split()).encode())
+    return h.hexdigest()[:16]
+
+
 HIPCC_FLAGS = [
     "-O3", "--offload-arch=gfx950", "-std=c++17", "-fPIC", "-shared",
     "-Wall",
@@ -32,7 +53,8 @@ def build_library(out: Path | None = None, extra: list[str] | None = None, verbo
     """Compile every HIP/C++ source of the library into one shared object."""
     out = Path(out) if out else LIB
     tmp = out.with_suffix(".so.tmp")
-    cmd = [hipcc(), *HIPCC_FLAGS, *(extra or []), f"-I{ROOT / 'include'}", f"-I{CSRC}",
+    cmd = [hipcc(), *HIPCC_FLAGS, f'-DPIR_KERNEL_DIGEST="{kernel_digest()}"', *(extra or []),
+           f"-I{ROOT / 'include'}", f"-I{CSRC}",
            *[str(CSRC / s) for s in (sources or SOURCES)], "-o", str(tmp)]
     if verbose:
         print(" ".join(cmd), flush=True)

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <atomic>
+#include <memory>
 #include <mutex>
 #include <vector>
 
@@ -119,10 +120,16 @@ struct CallCtx {
     uint32_t *status = nullptr;
     bool cleared = false;
     // The status word, or null if the default workspace cannot be located.
+    // Called before the call's first launch: it also drops an error code left
+    // in this thread by an earlier runtime call of the caller (an event or
+    // stream query that returned "not ready", say), so that the launch checks
+    // that follow see only the call's own launches.
     uint32_t *word()
     {
-        if (!status)
+        if (!status) {
+            (void)hipGetLastError();
             status = t_workspace ? t_workspace : default_workspace();
+        }
         return status;
     }
     // For the first k_fill_zero of the call: the word to clear, then null.
@@ -176,7 +183,7 @@ static uint32_t wave_hmax(uint32_t m) { return m >= 3 ? std::min<uint32_t>(HMAX3
 // wave_hmax(m) for the aligned subtree of height m holding a bin (or a table
 // slice); a single table gets the height of wave_height(), a launch of several
 // tables the largest (the tables together fill the GPU).
-static uint64_t plan_waves(WaveTask *ts, uint32_t count)
+static uint64_t plan_waves(WaveTask *ts, uint32_t count, uint32_t h_want = 0)
 {
     uint64_t items = 0;
     for (uint32_t i = 0; i < count; i++) {
@@ -188,7 +195,10 @@ static uint64_t plan_waves(WaveTask *ts, uint32_t count)
         // lane's subtree must lie in it too; whole tables and bins have m = n
         const uint32_t m = std::min<uint32_t>(t.n, bin_rows <= 2 ? 1 : ceil_log2(bin_rows));
         const uint32_t hmax = wave_hmax(m);
-        const uint32_t h = count == 1 ? wave_height(t.n_bins, bin_rows, t.n_groups, t.n, hmax) : hmax;
+        // a single table: the tuned height (clamped to what the rows allow) or the model's
+        const uint32_t h = count != 1 ? hmax
+                           : h_want   ? std::min(h_want, hmax)
+                                      : wave_height(t.n_bins, bin_rows, t.n_groups, t.n, hmax);
         t.h = h;
         t.chunks_per_bin = (uint32_t)chunks_per_bin(h);
         t.item_begin = (uint32_t)items;
@@ -218,13 +228,14 @@ constexpr int WAVE_CLASSES = 7;
 // Wave-kernel launch for up to MAX_TASKS tables of column class cls.  Plans
 // the tasks and clears their outputs first.
 template <class PRF>
-static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, int cls, CallCtx &ctx, hipStream_t st)
+static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, int cls, CallCtx &ctx, hipStream_t st,
+                        uint32_t h_want = 0)
 {
     WaveTasks W;
     bool any = false;
     for (uint32_t i = 0; i < count; i++)
         any |= ts[i].n_keys > 0;
-    const uint64_t items = plan_waves(ts, count);
+    const uint64_t items = plan_waves(ts, count, h_want);
     if (items == 0 && any)
         return PIR_ENOMEM;
     if (!ctx.word())
@@ -357,7 +368,8 @@ struct FusedPlan {
 // n is the keys' domain; the rows lie in an aligned subtree of height m <= n
 // from index row0 (m = n and row0 = 0 for a whole table), and chunks of 2^H
 // rows, H <= m, stay inside it.
-static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32_t n, uint32_t m, uint64_t row0)
+static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32_t n, uint32_t m, uint64_t row0,
+                            uint32_t q_want = 0)
 {
     FusedPlan p{};
     p.kch = dim <= 64 ? 1 : dim <= 128 ? 2 : 4;
@@ -368,6 +380,8 @@ static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32
     // words) despite their two waves per SIMD.
     const uint32_t qmax = p.kch == 2 ? 8u : (uint32_t)QMAX;
     p.Q = n_keys >= qmax ? qmax : (uint32_t)1 << ceil_log2(n_keys);
+    if (q_want && q_want <= qmax && (q_want & (q_want - 1)) == 0)
+        p.Q = q_want; // a tuned group size (a power of two the kernels are built for)
     const uint32_t lgS_max = ceil_log2(NT / p.Q);
     const uint32_t groups = (n_keys + p.Q - 1) / p.Q;
     const uint32_t want = ceil_log2((512 + groups - 1) / groups); // about one round of workgroup slots
@@ -384,6 +398,75 @@ static FusedPlan plan_fused(uint32_t n_keys, uint64_t rows, uint32_t dim, uint32
     p.g.n_chunks = (uint32_t)std::min<uint64_t>(chunks, 0xffffffffu);
     p.grid = chunks * groups;
     return p;
+}
+
+// ---------------------------------------------------------------------------
+// Tuned plans (pir_set_tuning): a table of entries measured by the project's
+// autotuner; a single-table call looks up its (PRF, aligned row height, row
+// width, batch size) and takes the fields the entry sets, the model the rest.
+struct TuneTable {
+    std::vector<pir_tune_t> e;
+};
+static std::shared_ptr<const TuneTable> g_tune;
+
+static std::shared_ptr<const TuneTable> tune_table() { return std::atomic_load(&g_tune); }
+
+static const pir_tune_t *find_tune(const TuneTable *T, uint32_t prf, uint32_t m, uint32_t dim, uint32_t keys)
+{
+    if (!T)
+        return nullptr;
+    for (const pir_tune_t &e : T->e)
+        if (e.prf_id == prf && e.n == m && dim >= e.dim_lo && dim <= e.dim_hi && keys >= e.keys_lo &&
+            keys <= e.keys_hi)
+            return &e;
+    return nullptr;
+}
+
+static bool tune_entry_ok(const pir_tune_t &e)
+{
+    return (e.prf_id == PIR_PRF_AES128 || e.prf_id == PIR_PRF_CHACHA20) && e.n >= 1 &&
+           e.n <= PIR_MAX_LOG_DOMAIN && e.dim_lo >= 1 && e.dim_lo <= e.dim_hi && e.dim_hi <= PIR_MAX_DIM &&
+           e.keys_lo >= 1 && e.keys_lo <= e.keys_hi && e.kernel <= PIR_KERNEL_SMALL_BATCH &&
+           e.subtree_log <= (uint32_t)HMAX3 && e.keys_per_item <= (uint32_t)QMAX &&
+           (e.keys_per_item & (e.keys_per_item - 1)) == 0 && (e.tail_keys <= 8 || e.tail_keys == PIR_TUNE_MODEL);
+}
+
+// How one table's call is planned: the remainder split off to a call of its
+// own, then (for a call without one) the kernel and its tuned parameters.
+struct Choice {
+    uint32_t tail = 0; // keys split off the end (0: none)
+    bool waves = false;
+    uint32_t h = 0;    // wave kernel: subtree height (0: the model's)
+    uint32_t q = 0;    // small-batch kernel: keys per workgroup (0: the model's)
+    bool tuned = false;
+};
+
+static Choice choose(uint32_t prf, uint32_t n_keys, uint32_t m, uint32_t dim)
+{
+    const std::shared_ptr<const TuneTable> T = tune_table();
+    const pir_tune_t *e = find_tune(T.get(), prf, m, dim, n_keys);
+    Choice c;
+    c.tuned = e != nullptr;
+    if (e && e->tail_keys != PIR_TUNE_MODEL) {
+        const uint32_t rem = n_keys % 16;
+        c.tail = (n_keys > 16 && rem >= 1 && rem <= e->tail_keys) ? rem : 0;
+    } else {
+        c.tail = split_tail(n_keys, m);
+    }
+    if (c.tail)
+        return c; // the head and the remainder are planned as calls of their own
+    const bool can_wave = m >= 3 && dim <= 128;
+    if (e && e->kernel == PIR_KERNEL_WAVES)
+        c.waves = can_wave;
+    else if (e && e->kernel == PIR_KERNEL_SMALL_BATCH)
+        c.waves = false;
+    else
+        c.waves = use_wave_kernel(prf, n_keys, m, dim);
+    if (e) {
+        c.h = e->subtree_log;
+        c.q = e->keys_per_item;
+    }
+    return c;
 }
 
 // Validates a call over the table rows holding indices row0 .. row0 + rows -
@@ -407,7 +490,8 @@ static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_str
         ((uintptr_t)d_table % 4) || ((uintptr_t)d_out % 4))
         return PIR_EINVAL;
 
-    if (const uint32_t tail = split_tail(n_keys, m)) {
+    const Choice ch = choose(PRF::id, n_keys, m, dim);
+    if (const uint32_t tail = ch.tail) {
         const uint32_t head = n_keys - tail;
         const int rc = answer_range<PRF>(d_keys, head, key_stride, n, row0, d_table, rows, dim, d_out, ctx, st);
         if (rc != PIR_OK)
@@ -416,7 +500,7 @@ static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_str
                                  d_out + (size_t)head * dim, ctx, st);
     }
 
-    if (use_wave_kernel(PRF::id, n_keys, m, dim)) {
+    if (ch.waves) {
         WaveTask t{};
         t.table = d_table;
         t.keys = d_keys;
@@ -427,10 +511,10 @@ static int answer_range(const uint8_t *d_keys, uint32_t n_keys, uint32_t key_str
         t.n_keys = n_keys;
         t.n = n;
         t.n_bins = 1;
-        return launch_waves<PRF>(&t, 1, key_stride, wave_class(dim, vec_aligned(d_table)), ctx, st);
+        return launch_waves<PRF>(&t, 1, key_stride, wave_class(dim, vec_aligned(d_table)), ctx, st, ch.h);
     }
 
-    const FusedPlan p = plan_fused(n_keys, rows, dim, n, m, row0);
+    const FusedPlan p = plan_fused(n_keys, rows, dim, n, m, row0, ch.q);
     if (p.grid >= ((uint64_t)1 << 31))
         return PIR_ENOMEM;
     const Geometry &g = p.g;
@@ -613,16 +697,23 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
     const bool aes = prf_id == PIR_PRF_AES128;
     *out = pir_plan_t{};
     out->n = n;
-    out->tail_keys = split_tail(n_keys, n);
-    n_keys -= out->tail_keys; // the rest describes the first launch
-    if (use_wave_kernel(prf_id, n_keys, n, dim)) {
+    Choice c = choose(prf_id, n_keys, n, dim);
+    bool tuned = c.tuned;
+    out->tail_keys = c.tail;
+    if (c.tail) { // the rest describes the first launch, over the head
+        n_keys -= c.tail;
+        c = choose(prf_id, n_keys, n, dim);
+        tuned |= c.tuned;
+    }
+    out->source = tuned ? PIR_PLAN_TUNED : PIR_PLAN_MODEL;
+    if (c.waves) {
         WaveTask t{};
         t.rows = rows;
         t.dim = dim;
         t.n_keys = n_keys;
         t.n = n;
         t.n_bins = 1;
-        const uint64_t items = plan_waves(&t, 1);
+        const uint64_t items = plan_waves(&t, 1, c.h);
         if (items == 0)
             return PIR_ENOMEM;
         out->kernel = PIR_KERNEL_WAVES;
@@ -637,14 +728,15 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
         out->bfs_levels = 0;
         return PIR_OK;
     }
-    const FusedPlan p = plan_fused(n_keys, rows, dim, n, n, 0);
+    const FusedPlan p = plan_fused(n_keys, rows, dim, n, n, 0, c.q);
     if (p.grid >= ((uint64_t)1 << 31))
         return PIR_ENOMEM;
     out->kernel = PIR_KERNEL_SMALL_BATCH;
     out->items = p.grid;
     out->workgroups = p.grid;
     out->lanes_per_workgroup = NT;
-    out->lds_bytes = aes ? (uint32_t)sizeof(Smem<AesPrf::TAB_WORDS>) : (uint32_t)sizeof(Smem<ChaChaPrf::TAB_WORDS>);
+    out->lds_bytes = (aes ? (uint32_t)sizeof(Smem<AesPrf::TAB_WORDS>) : (uint32_t)sizeof(Smem<ChaChaPrf::TAB_WORDS>)) +
+                     (p.Q <= 2 ? p.Q * 64 * PIR_MAX_LOG_DOMAIN : 0u); // one or two keys' codewords
     out->keys_per_item = p.Q;
     out->rows_per_item = (uint64_t)1 << p.g.H;
     out->subtree_log = p.g.H - p.g.lgS;
@@ -652,6 +744,34 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
     out->bfs_levels = p.g.lgS;
     return PIR_OK;
 }
+
+int pir_set_tuning(const pir_tune_t *entries, uint32_t count)
+{
+    if ((count && !entries) || count > PIR_TUNE_MAX_ENTRIES)
+        return PIR_EINVAL;
+    for (uint32_t i = 0; i < count; i++)
+        if (!tune_entry_ok(entries[i]))
+            return PIR_EINVAL;
+    std::shared_ptr<const TuneTable> T;
+    if (count) {
+        auto t = std::make_shared<TuneTable>();
+        t->e.assign(entries, entries + count);
+        T = t;
+    }
+    std::atomic_store(&g_tune, T);
+    return PIR_OK;
+}
+
+uint32_t pir_tuning_count(void)
+{
+    const std::shared_ptr<const TuneTable> T = tune_table();
+    return T ? (uint32_t)T->e.size() : 0u;
+}
+
+#ifndef PIR_KERNEL_DIGEST
+#define PIR_KERNEL_DIGEST "unknown"
+#endif
+const char *pir_kernel_digest(void) { return PIR_KERNEL_DIGEST; }
 
 int pir_plan_bins(uint32_t prf_id, uint64_t rows, uint32_t dim, uint32_t n_clients, uint32_t bin_log,
                   pir_plan_t *out)

@@ -24,7 +24,10 @@ PRFS = {"aes128": PRF_AES128, "chacha20": PRF_CHACHA20}
 EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_prf", "pir_answer_slice",
            "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_plan", "pir_plan_bins",
            "pir_reconstruct", "pir_workspace_size", "pir_set_workspace", "pir_workspace_status",
-           "pir_check_status", "pir_strerror", "pir_last_hip_error")
+           "pir_check_status", "pir_strerror", "pir_last_hip_error", "pir_set_tuning", "pir_tuning_count",
+           "pir_kernel_digest")
+PLAN_MODEL, PLAN_TUNED = 0, 1
+TUNE_MODEL = 0xFFFFFFFF
 WORKSPACE_BYTES = 256
 STATUS_BAD_KEY = 1
 KERNEL_WAVES, KERNEL_SMALL_BATCH = 1, 2
@@ -51,7 +54,14 @@ class PirPlan(ctypes.Structure):
                 ("lds_bytes", ctypes.c_uint32), ("keys_per_item", ctypes.c_uint32),
                 ("subtree_log", ctypes.c_uint32), ("rows_per_item", ctypes.c_uint64),
                 ("descent_levels", ctypes.c_uint32), ("bfs_levels", ctypes.c_uint32),
-                ("tail_keys", ctypes.c_uint32)]
+                ("tail_keys", ctypes.c_uint32), ("source", ctypes.c_uint32)]
+
+
+class PirTune(ctypes.Structure):
+    _fields_ = [("prf_id", ctypes.c_uint32), ("n", ctypes.c_uint32), ("dim_lo", ctypes.c_uint32),
+                ("dim_hi", ctypes.c_uint32), ("keys_lo", ctypes.c_uint32), ("keys_hi", ctypes.c_uint32),
+                ("kernel", ctypes.c_uint32), ("subtree_log", ctypes.c_uint32),
+                ("keys_per_item", ctypes.c_uint32), ("tail_keys", ctypes.c_uint32)]
 
 
 class PirBins(ctypes.Structure):
@@ -68,6 +78,10 @@ def load(path: Path | None = None):
     if not p.exists():
         raise ImportError(f"{p} is missing: build it with `python -m paper_2301_10904_amd.build` "
                           "(there is no fallback path)")
+    # One HIP runtime per process: PyTorch's (it supplies the device memory
+    # and streams) is loaded first, and the library binds to the same one.
+    # Loaded the other way round, the two disagree about the devices.
+    import torch  # noqa: F401
     lib = ctypes.CDLL(str(p))
     u8p = ctypes.POINTER(ctypes.c_uint8)
     u32p = ctypes.POINTER(ctypes.c_uint32)
@@ -111,6 +125,12 @@ def load(path: Path | None = None):
     lib.pir_set_workspace.argtypes = [ctypes.c_void_p, ctypes.c_size_t]
     lib.pir_workspace_status.restype = ctypes.c_int
     lib.pir_workspace_status.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+    lib.pir_set_tuning.restype = ctypes.c_int
+    lib.pir_set_tuning.argtypes = [ctypes.POINTER(PirTune), ctypes.c_uint32]
+    lib.pir_tuning_count.restype = ctypes.c_uint32
+    lib.pir_tuning_count.argtypes = []
+    lib.pir_kernel_digest.restype = ctypes.c_char_p
+    lib.pir_kernel_digest.argtypes = []
     lib.pir_reconstruct.restype = ctypes.c_int
     lib.pir_reconstruct.argtypes = [u32p, u32p, ctypes.c_uint32, u32p]
     lib.pir_check_status.restype = ctypes.c_int
@@ -295,6 +315,27 @@ def plan(n_keys: int, rows: int, dim: int, prf=PRF_AES128) -> dict:
     p = PirPlan()
     _check(load().pir_plan(prf_id(prf), n_keys, rows, dim, ctypes.byref(p)), "pir_plan")
     return {name: getattr(p, name) for name, _ in PirPlan._fields_}
+
+
+TUNE_FIELDS = tuple(name for name, _ in PirTune._fields_)
+
+
+def set_tuning(entries) -> None:
+    """Replace the library's tuned plan table (pir_set_tuning) with `entries`,
+    a list of dicts with the fields of pir_tune_t (an empty list clears it)."""
+    arr = (PirTune * max(1, len(entries)))()
+    for i, e in enumerate(entries):
+        arr[i] = PirTune(*[int(e[f]) for f in TUNE_FIELDS])
+    _check(load().pir_set_tuning(arr, len(entries)), "pir_set_tuning")
+
+
+def tuning_count() -> int:
+    return int(load().pir_tuning_count())
+
+
+def kernel_digest() -> str:
+    """Fingerprint of the kernel sources the loaded library was built from."""
+    return load().pir_kernel_digest().decode()
 
 
 def plan_bins(rows: int, dim: int, n_clients: int, bin_log: int, prf=PRF_AES128) -> dict:

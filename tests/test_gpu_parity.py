@@ -314,6 +314,46 @@ def test_large_table_2p25_x64(O, pirmod):
     torch.cuda.empty_cache()
 
 
+@pytest.mark.parametrize("pairs", [1024, 2048])
+def test_large_table_2p25_x64_large_batches(O, pirmod, pairs):
+    """The 2^25 x 64 table (8 GiB) with the large batches of the 1024..4096
+    key workload: 2048 and 4096 keys per launch.  Every reconstruction equals
+    T[alpha] on the dense table; on a sparse copy of the same shape one key
+    of every group of 16 (the wave kernel's key group) is checked per server
+    against the oracle's point evaluation, and every reconstruction against
+    the support."""
+    import torch
+
+    rows, dim, seed = 1 << 25, 64, 40 + pairs
+    T = W.make_table(rows, dim, seed, device="cuda")
+    alphas = W.uniform_indices(rows, pairs, seed)
+    K0, K1 = oracle_keys(O, 25, alphas, seed)
+    keys = np.concatenate([K0, K1])
+    keys_dev = torch.from_numpy(keys).cuda()
+    assert pirmod.plan(2 * pairs, rows, dim)["kernel"] == pirmod.KERNEL_WAVES
+    out = pirmod.answer(keys_dev, T)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    recon = (got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF
+    assert (recon.astype(np.uint32) == W.table_rows_np(alphas, dim, seed)).all()
+    del T, out
+    torch.cuda.empty_cache()
+    Ts, sup, vals = make_sparse(rows, dim, seed, 8, "cuda")
+    out = pirmod.answer(keys_dev, Ts)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy().view(np.uint32)
+    rng = np.random.default_rng(seed)
+    sample = np.arange(0, 2 * pairs, 16) + rng.integers(0, 16, size=2 * pairs // 16)
+    assert (got[sample] == sparse_answers(O, keys[sample], sup, vals)).all()
+    dense_rows = {int(j): v for j, v in zip(sup, vals)}
+    for p in range(pairs):
+        r = (got[p].astype(np.uint64) + got[pairs + p]) & 0xFFFFFFFF
+        w = dense_rows.get(int(alphas[p]), np.zeros(dim, np.uint32))
+        assert (r.astype(np.uint32) == w).all()
+    del Ts
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("pairs,dim", [(1, 64), (1, 32), (2, 64), (3, 16), (7, 32)])
 def test_small_batches_deep_tree(O, pirmod, pairs, dim):
     """Fewer than 16 keys on a 2^18-row table: the small-batch kernel with a

@@ -175,3 +175,28 @@ def test_multi_table_call_reports_once(O, pirmod):
             assert pirmod.workspace_status(ws) == want, bad_at
     finally:
         pirmod.set_workspace(None)
+
+
+def test_a_not_ready_query_before_a_call_is_not_an_error(O, pirmod):
+    """An event query that finds its event not reached leaves "not ready" as
+    the thread's last runtime error; the next library call must not mistake
+    it for a failure of its own launches."""
+    import torch
+
+    rows, dim = 1 << 16, 64
+    T = W.make_table(rows, dim, 35)
+    Td = T.cuda()
+    big = torch.from_numpy(keyset(O, rows, 512, 35)).cuda()
+    small = keyset(O, rows, 3, 36)
+    torch.cuda.synchronize()
+    seen_not_ready = False
+    for _ in range(3):
+        pirmod.answer(big, Td)  # a few ms of work
+        ev = torch.cuda.Event()
+        ev.record()
+        seen_not_ready |= not ev.query()
+        got = pirmod.answer(torch.from_numpy(small).cuda(), Td)  # raises on a launch error
+        torch.cuda.synchronize()
+        want = O.answer_batch(small, T.numpy().view(np.uint32), nthreads=cpu_threads())
+        assert (got.cpu().numpy().view(np.uint32) == want).all()
+    assert seen_not_ready
