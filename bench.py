@@ -235,6 +235,9 @@ def main():
                          "sizes: 2^14, 2^20, 2^22 rows x 64 (the table sizes of the paper's GPU/CPU comparison); "
                          "batchsweep: latency and throughput for 1..1024 keys per call on 2^20 x 64; "
                          "shards: one GPU's share of the 2^25 x 64 table split over 2, 4, 8 GPUs (row slices)")
+    ap.add_argument("--plans", default="tuned", choices=["tuned", "model"],
+                    help="tuned: the autotuner's cache for this system where it applies (default); "
+                         "model: the library's cost model only")
     ap.add_argument("--prf", default="aes128", choices=["aes128", "chacha20"],
                     help="the DPF tree's PRF (section 3.2.6): AES-128 (default) or ChaCha20")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
@@ -271,6 +274,14 @@ def main():
     from paper_2301_10904_amd import workloads as W
 
     pir.load()
+    # the autotuner's plans where its cache was measured on this system (the
+    # cost model plans the rest, and everything with --plans model)
+    tuning = {"applied": False, "entries": 0, "reason": "--plans model"}
+    if args.plans == "tuned":
+        from paper_2301_10904_amd import autotune
+
+        tuning = autotune.load()
+    args.tuning = {k: tuning[k] for k in ("applied", "entries", "reason")}
     if args.mode != "batch":
         return other_modes(args)
     dev = torch.device("cuda:0")
@@ -405,6 +416,9 @@ def main():
         "measured_peaks": peaks,
         "cpu_baseline": cpu,
         "large_table": large,
+        "plan": {"kernel": kernel, "source": "tuned" if plan["source"] == pir.PLAN_TUNED else "model",
+                 "subtree_log": plan["subtree_log"], "keys_per_item": plan["keys_per_item"],
+                 "tuning": args.tuning},
     }
     print(json.dumps(res), flush=True)
     if not recon_ok or (large and not large["exact"]):
@@ -639,7 +653,7 @@ def other_modes(args):
     dev = torch.device("cuda:0")
     prf = args.prf
     line = {"metric": METRIC, "unit": "server queries/s", "n_gpus": 1, "higher_is_better": True,
-            "dtype": "u32", "data": "synthetic", "mode": args.mode, "prf": prf}
+            "dtype": "u32", "data": "synthetic", "mode": args.mode, "prf": prf, "plans": args.tuning}
     if args.mode == "small":
         rows, dim = 1 << 14, 16
         T = W.make_table(rows, dim, 1, device=dev)
@@ -791,6 +805,21 @@ def batch_sweep(args):
     K0, K1 = pir.gen_batch(20, a, W.key_seeds(512, seed), prf=args.prf)
     allk = torch.from_numpy(np.concatenate([K0, K1])).to(dev)  # key i pairs with key 512 + i
     want = W.table_rows_np(a, dim, seed)
+    # the plans in force (the autotuner's where its cache applies) and, beside
+    # them, the cost model's alone: the same calls timed both ways, alternating
+    tuned_entries = []
+    if args.tuning["applied"]:
+        from paper_2301_10904_amd import autotune
+
+        tuned_entries = autotune.entries_of(json.loads(autotune.default_path(
+            autotune.system_identity()["arch"]).read_text()))
+
+    def describe(plan, B):
+        kern = "waves" if plan["kernel"] == pir.KERNEL_WAVES else "small_batch"
+        if plan["tail_keys"]:
+            kern += f" ({B - plan['tail_keys']} keys) + remainder ({plan['tail_keys']} keys)"
+        return kern
+
     runs, ok = [], True
     for B in (1, 2, 4, 8, 9, 12, 15, 16, 17, 24, 32, 40, 64, 100, 128, 256, 512, 520, 1024):
         if B == 1:
@@ -799,21 +828,46 @@ def batch_sweep(args):
             half = B // 2
             keys = torch.cat([allk[:half], allk[512:512 + half]] + ([allk[half:half + 1]] if B % 2 else [])).contiguous()
         out = torch.empty((keys.shape[0], dim), dtype=torch.int32, device=dev)
-        steps = 50 if B <= 64 else 10
-        sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=args.prf), steps, 3)
-        if B >= 2:
-            got = out.cpu().numpy().view(np.uint32)
-            half = B // 2
-            rec = ((got[:half].astype(np.uint64) + got[half:2 * half]) & 0xFFFFFFFF).astype(np.uint32)
-            ok &= bool((rec == want[:half]).all())
-        plan = pir.plan(B, rows, dim, prf=args.prf)
-        kern = "waves" if plan["kernel"] == pir.KERNEL_WAVES else "small_batch"
-        if plan["tail_keys"]:
-            kern += f" ({B - plan['tail_keys']} keys) + small_batch ({plan['tail_keys']} keys)"
-        runs.append({"keys": B, "kernel": kern,
-                     "p50_ms": round(percentile(ms, 50), 4), "p99_ms": round(percentile(ms, 99), 4),
-                     "server_qps": round(B / sec, 1)})
-    return {"value": runs[-1]["server_qps"], "exact": ok, "batchsweep": runs,
+        steps = 60 if B <= 64 else 12
+        which_all = ("tuned", "model") if tuned_entries else ("model",)
+        tables = {"tuned": tuned_entries, "model": []}
+        for which in which_all:  # warm-up, and the exactness of each plan
+            pir.set_tuning(tables[which])
+            for _ in range(3):
+                pir.answer(keys, T, out, prf=args.prf)
+            torch.cuda.synchronize()
+            if B >= 2:
+                got = out.cpu().numpy().view(np.uint32)
+                half = B // 2
+                rec = ((got[:half].astype(np.uint64) + got[half:2 * half]) & 0xFFFFFFFF).astype(np.uint32)
+                ok &= bool((rec == want[:half]).all())
+        # one call of each in turn, each bracketed by its own events (queued
+        # back to back, as a server would), so that both plans see the same
+        # state of the GPU
+        evs = {w: [] for w in which_all}
+        for _ in range(steps):
+            for which in which_all:
+                pir.set_tuning(tables[which])
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                pir.answer(keys, T, out, prf=args.prf)
+                e1.record()
+                evs[which].append((e0, e1))
+        torch.cuda.synchronize()
+        ms = {w: [a.elapsed_time(b) for a, b in evs[w]] for w in which_all}
+        row = {"keys": B}
+        for which in which_all:
+            pir.set_tuning(tables[which])
+            row[which] = {"kernel": describe(pir.plan(B, rows, dim, prf=args.prf), B),
+                          "p50_ms": round(percentile(ms[which], 50), 4),
+                          "p99_ms": round(percentile(ms[which], 99), 4),
+                          "server_qps": round(B / (percentile(ms[which], 50) * 1e-3), 1)}
+        if "tuned" in row:
+            row["tuned_vs_model_p50"] = round(row["tuned"]["p50_ms"] / row["model"]["p50_ms"], 4)
+        runs.append(row)
+    pir.set_tuning(tuned_entries)
+    best = runs[-1].get("tuned", runs[-1]["model"])
+    return {"value": best["server_qps"], "exact": ok, "batchsweep": runs, "tuning": args.tuning,
             "config": {"workload": "one table 2^20 x 64 uint32, 1..1024 keys per call (both servers' keys), "
                                    "uniform alpha", "prf": args.prf}}
 
