@@ -307,7 +307,13 @@ int pir_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim, uint32
  *     the process: calls that overlap in time on one device overwrite each
  *     other's status in it, so concurrent streams should each bind their own.
  * The calls clear the word with a kernel, never a memset, so they may be
- * captured in a HIP graph; a replay reports its own status. */
+ * captured in a HIP graph; a replay reports its own status.
+ *
+ * For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): the answer calls never
+ * allocate, and with no workspace bound they use the library's own array of
+ * PIR_WORKSPACE_BYTES per device (held until the process ends), so they need
+ * no buffer beyond their inputs and outputs. */
 #define PIR_WORKSPACE_BYTES 256u  /* size of a status workspace */
 #define PIR_STATUS_BAD_KEY 1u     /* status bit: a key had a bad header */
 
