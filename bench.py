@@ -148,6 +148,42 @@ def pmc_summary(paths, kernel_substr="k_pir_waves", copy_mib=256):
     return avg, scale, len(per)
 
 
+def short_kernel_name(name: str) -> str:
+    """`k_pir_waves<AesPrf, 4, true>` from the demangled name rocprofv3 prints."""
+    import re
+
+    name = re.sub(r"\(anonymous namespace\)::", "", name)
+    name = re.sub(r"^void ", "", name)
+    depth, out = 0, []
+    for ch in name:  # drop the argument list
+        if ch == "(" and depth == 0:
+            break
+        depth += ch == "<"
+        depth -= ch == ">"
+        out.append(ch)
+    return "".join(out).strip()
+
+
+def trace_summary(path) -> list[dict]:
+    """Per (kernel, grid size) averages of a rocprofv3 --kernel-trace CSV: one
+    kernel launched over different grids (the 2^20 and the 2^25 launches of the
+    default line) is listed once per grid."""
+    import collections
+    import csv
+
+    groups = collections.defaultdict(list)
+    for r in csv.DictReader(open(path)):
+        key = (short_kernel_name(r["Kernel_Name"]), int(r["Grid_Size_X"]), int(r["Workgroup_Size_X"]))
+        groups[key].append((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6)
+    total = sum(sum(v) for v in groups.values())
+    rows = []
+    for (name, grid, wg), ms in groups.items():
+        rows.append({"kernel": name, "workgroups": grid // wg, "lanes_per_workgroup": wg, "calls": len(ms),
+                     "avg_ms": sum(ms) / len(ms), "min_ms": min(ms), "max_ms": max(ms),
+                     "pct": 100 * sum(ms) / total})
+    return sorted(rows, key=lambda r: -r["pct"])
+
+
 def percentile(xs, p):
     return float(np.percentile(np.asarray(xs, dtype=np.float64), p))
 
@@ -242,12 +278,24 @@ def main():
                     help="the DPF tree's PRF (section 3.2.6): AES-128 (default) or ChaCha20")
     ap.add_argument("--pmc-summary", nargs="+", metavar="CSV",
                     help="summarise rocprofv3 --pmc counter CSVs of this benchmark and exit")
+    ap.add_argument("--trace-summary", metavar="CSV",
+                    help="summarise a rocprofv3 --kernel-trace CSV per kernel and grid size and exit")
+    ap.add_argument("--trace-rows", type=int, default=12, help="rows of --trace-summary")
     ap.add_argument("--pmc-kernel", default="k_pir_waves",
                     help="with --pmc-summary: the kernel whose dispatches are summarised (a name substring)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="also run a plain device copy of MIB MiB (read + write) three times, "
                          "to scale HBM traffic counters")
     args = ap.parse_args()
+
+    if args.trace_summary:
+        rows = trace_summary(args.trace_summary)
+        print("| Kernel | Workgroups | Calls | Avg ms | Min ms | Max ms | % of GPU time |")
+        print("|---|---|---|---|---|---|---|")
+        for r in rows[:args.trace_rows]:
+            print(f"| `{r['kernel']}` | {r['workgroups']} x {r['lanes_per_workgroup']} | {r['calls']} | "
+                  f"{r['avg_ms']:.4f} | {r['min_ms']:.4f} | {r['max_ms']:.4f} | {r['pct']:.2f} |")
+        return
 
     if args.pmc_summary:
         avg, scale, dispatches = pmc_summary(args.pmc_summary, kernel_substr=args.pmc_kernel,
