@@ -200,3 +200,82 @@ def test_a_not_ready_query_before_a_call_is_not_an_error(O, pirmod):
         want = O.answer_batch(small, T.numpy().view(np.uint32), nthreads=cpu_threads())
         assert (got.cpu().numpy().view(np.uint32) == want).all()
     assert seen_not_ready
+
+
+@pytest.mark.parametrize("bound", [False, True])
+@pytest.mark.parametrize("prf", [0, 1])
+def test_one_launch_calls_leave_the_workspace_clean(O, pirmod, bound, prf):
+    """A run of calls of one or two keys (the single-query path), a bad key
+    among them and a larger call in between, on the library's own workspace
+    or a bound one: each answers as the oracle and reports its own status."""
+    import torch
+
+    shapes = [(1 << 14, 64), (3000, 16), (1 << 16, 100)]
+    ws = pirmod.workspace() if bound else None
+    pirmod.set_workspace(ws)
+    try:
+        for i, (rows, dim) in enumerate(shapes):
+            seed = 200 + 10 * i + prf
+            n = max(1, (rows - 1).bit_length())
+            T = W.make_table(rows, dim, seed)
+            Tn, Td = T.numpy().view(np.uint32), T.cuda()
+            a = W.uniform_indices(rows, 20, seed)
+            K, _ = O.gen_batch(n, a, W.key_seeds(20, seed), prf_id=prf)
+            want = O.answer_batch(K, Tn, nthreads=cpu_threads())
+            bad = K[:2].copy()
+            bad[1, 0] = 9  # bad version on the second key
+            for keys, idx, st in ((K[:1], [0], 0), (K[:2], [0, 1], 0), (bad, [0], 1), (K[1:2], [1], 0),
+                                  (K, list(range(20)), 0), (K[:1], [0], 0)):
+                assert pirmod.plan(len(keys), rows, dim, prf=prf)["workgroups"] > 1
+                out = pirmod.answer(torch.from_numpy(np.ascontiguousarray(keys)).cuda(), Td, prf=prf)
+                torch.cuda.synchronize()
+                got = out.cpu().numpy().view(np.uint32)
+                status = pirmod.workspace_status(ws) if bound else pirmod.check_status()
+                assert status == (pirmod.PIR_EKEY if st else pirmod.PIR_OK), (i, len(keys), st)
+                if st:
+                    assert (got[0] == want[0]).all() and (got[1] == 0).all()
+                else:
+                    assert (got == want[idx]).all(), (i, len(keys))
+    finally:
+        pirmod.set_workspace(None)
+
+
+def test_one_key_call_replays_in_a_graph(O, pirmod):
+    """A captured one-key call replayed with new keys, with eager calls on the
+    library's own workspace in between: every replay answers as the oracle
+    and reports its status in the bound workspace."""
+    import torch
+
+    rows, dim = 1 << 15, 64
+    T = W.make_table(rows, dim, 37)
+    Tn, Td = T.numpy().view(np.uint32), T.cuda()
+    sets = [keyset(O, rows, 1, 300 + i) for i in range(3)]
+    bad = sets[0].copy()
+    bad[0, 2] = 3
+    keys = torch.from_numpy(sets[0]).cuda()
+    out = torch.empty((1, dim), dtype=torch.int32, device="cuda")
+    ws = pirmod.workspace()
+    pirmod.set_workspace(ws)
+    try:
+        pirmod.answer(keys, Td, out)  # eager, before capture
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            pirmod.answer(keys, Td, out)
+    finally:
+        pirmod.set_workspace(None)
+    torch.cuda.synchronize()
+    for rep, ks in enumerate([sets[1], bad, sets[2], sets[0], bad, sets[1]]):
+        keys.copy_(torch.from_numpy(ks).cuda())
+        out.fill_(-1)
+        g.replay()
+        torch.cuda.synchronize()
+        got = out.cpu().numpy().view(np.uint32)
+        if ks is bad:
+            assert pirmod.workspace_status(ws) == pirmod.PIR_EKEY and (got == 0).all(), rep
+        else:
+            assert pirmod.workspace_status(ws) == pirmod.PIR_OK, rep
+            assert (got == O.answer_batch(ks, Tn, nthreads=cpu_threads())).all(), rep
+        other = pirmod.answer(torch.from_numpy(sets[2]).cuda(), Td)  # eager work on the library's workspace
+        torch.cuda.synchronize()
+        assert (other.cpu().numpy().view(np.uint32) == O.answer_batch(sets[2], Tn, nthreads=cpu_threads())).all()
