@@ -473,7 +473,7 @@ def main():
         sys.exit(1)
 
 
-KERNEL_NAMES = {1: "k_pir_waves", 2: "k_pir_fused"}
+KERNEL_NAMES = {1: "k_pir_waves", 2: "k_pir_fused", 3: "k_pir_stream"}
 
 
 def rooflines(prf: str, n: int, keys: int, dim: int, kern_s: float, kernel: str):

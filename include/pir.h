@@ -216,6 +216,9 @@ int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables
  * keys, or sizes pir_answer rejects; PIR_ENOMEM where pir_answer would. */
 #define PIR_KERNEL_WAVES 1       /* batched: up to 16 keys per wave, int8 matrix cores */
 #define PIR_KERNEL_SMALL_BATCH 2 /* small batches (or rows > 128 words): 512-lane workgroups */
+#define PIR_KERNEL_STREAM 3      /* one AES-128 key on a table above 256 MiB with rows of at
+                                    most 64 words (a multiple of 4, 16-byte aligned): tree
+                                    and table-stream waves in 512-lane workgroups */
 typedef struct {
     uint32_t kernel;              /* PIR_KERNEL_* */
     uint32_t n;                   /* key domain: ceil(log2 rows), at least 1 */
@@ -316,6 +319,8 @@ int pir_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim, uint32
  * no buffer beyond their inputs and outputs. */
 #define PIR_WORKSPACE_BYTES 256u  /* size of a status workspace */
 #define PIR_STATUS_BAD_KEY 1u     /* status bit: a key had a bad header */
+#define PIR_STATUS_STALLED 2u     /* status bit: a kernel gave up a bounded wait (never expected;
+                                     the call's output is then not valid) */
 
 /* Bytes of a status workspace: PIR_WORKSPACE_BYTES. */
 size_t pir_workspace_size(void);

@@ -361,46 +361,19 @@ __device__ __forceinline__ uint4 row_load4(const uint32_t *p)
 // VEC4: dim is a multiple of 4 and the table 16-byte aligned (16-byte row
 // segments are aligned); STREAM:
 // table rows are read with row_load4<true> (single keys on large tables).
-template <class PRF, int Q, int KCH, bool VEC4, bool STREAM>
-__global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ keys, uint32_t n_keys,
-                                                  uint32_t stride, const uint32_t *__restrict__ table,
-                                                  uint64_t rows, uint32_t dim, uint32_t *__restrict__ out,
-                                                  Geometry g, uint32_t *status)
+// The top of a small-batch item's trees, shared by k_pir_fused and
+// k_pir_stream (all lanes of the workgroup call it): the PRF's tables in LDS,
+// the Q keys' headers (sm.keyok, a bad one flagged in *status), the descent
+// from each root to the chunk's subtree root at depth n - H, and lgS
+// breadth-first levels below it, after which sm.u.bfs holds each key's 2^lgS
+// nodes at depth n - H + lgS, key-major.  cw_of(q) gives key q's codewords.
+template <class PRF, int Q, class CWOF>
+__device__ __forceinline__ void expand_top(Smem<PRF::TAB_WORDS> &sm, const PRF &P, const CWOF &cw_of,
+                                           const uint8_t *__restrict__ keys, uint32_t n_keys, uint32_t stride,
+                                           uint32_t grp, uint64_t row_base, const Geometry &g, uint32_t lgS,
+                                           uint32_t *status)
 {
-    __shared__ Smem<PRF::TAB_WORDS> sm;
-    // CWL: one or two keys per workgroup keep their codewords in LDS (2 KiB
-    // each at most), so that the dependent chain of node evaluations from the
-    // root down never waits on a load from memory
-    constexpr bool CWL = Q <= 2;
-    constexpr uint32_t CW_WORDS = 64 * PIR_MAX_LOG_DOMAIN / 4; // one key's codewords
-    __shared__ uint4 s_cw[CWL ? Q * CW_WORDS / 4 : 1];
-
-    const uint32_t tid = threadIdx.x;
-    const uint32_t lane = tid & 63, wave = tid >> 6;
-    const uint32_t blk = xcd_block();
-    const uint32_t grp = blk % g.n_groups;
-    const uint32_t chunk = blk / g.n_groups;
-    const uint64_t row_base = (uint64_t)chunk << g.H;
-    const PRF P(sm.tab, lane);
-
-    if constexpr (CWL) {
-        // key q's 4n codeword vectors to s_cw[q CW_WORDS / 4 ..]; a key past
-        // the batch leaves its slots unused
-        const uint32_t per = 4 * g.n;
-        for (uint32_t i = tid; i < Q * per; i += NT) {
-            const uint32_t q = i / per, j = i % per, kq = grp * Q + q;
-            if (kq < n_keys)
-                s_cw[q * (CW_WORDS / 4) + j] = reinterpret_cast<const uint4 *>(keys + (size_t)kq * stride + 32)[j];
-        }
-    }
-    // the codewords of key q of the group
-    auto cw_of = [&](uint32_t q) {
-        if constexpr (CWL)
-            return CwLds{(lds_u8 *)(s_cw + q * (CW_WORDS / 4))};
-        else
-            return cw_global(KeyView{keys + (size_t)(grp * Q + q) * stride});
-    };
-
+    const uint32_t tid = threadIdx.x, lane = tid & 63;
     PRF::fill(sm.tab, tid, NT);
 
     // key headers; roots of the keys
@@ -450,7 +423,7 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
     __syncthreads();
 
     // breadth-first expansion in LDS, in place: Q * 2^lgS nodes at depth dtop + lgS
-    for (uint32_t l = 1; l <= g.lgS; l++) {
+    for (uint32_t l = 1; l <= lgS; l++) {
         const uint32_t half = 1u << (l - 1);
         if (PRF::QUAD && 4 * Q * half <= NT) {
             // a quad of lanes per node while the level is narrow
@@ -487,6 +460,50 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         }
         __syncthreads();
     }
+
+}
+
+template <class PRF, int Q, int KCH, bool VEC4, bool STREAM>
+__global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ keys, uint32_t n_keys,
+                                                  uint32_t stride, const uint32_t *__restrict__ table,
+                                                  uint64_t rows, uint32_t dim, uint32_t *__restrict__ out,
+                                                  Geometry g, uint32_t *status)
+{
+    __shared__ Smem<PRF::TAB_WORDS> sm;
+    // CWL: one or two keys per workgroup keep their codewords in LDS (2 KiB
+    // each at most), so that the dependent chain of node evaluations from the
+    // root down never waits on a load from memory
+    constexpr bool CWL = Q <= 2;
+    constexpr uint32_t CW_WORDS = 64 * PIR_MAX_LOG_DOMAIN / 4; // one key's codewords
+    __shared__ uint4 s_cw[CWL ? Q * CW_WORDS / 4 : 1];
+
+    const uint32_t tid = threadIdx.x;
+    const uint32_t lane = tid & 63, wave = tid >> 6;
+    const uint32_t blk = xcd_block();
+    const uint32_t grp = blk % g.n_groups;
+    const uint32_t chunk = blk / g.n_groups;
+    const uint64_t row_base = (uint64_t)chunk << g.H;
+    const PRF P(sm.tab, lane);
+
+    if constexpr (CWL) {
+        // key q's 4n codeword vectors to s_cw[q CW_WORDS / 4 ..]; a key past
+        // the batch leaves its slots unused
+        const uint32_t per = 4 * g.n;
+        for (uint32_t i = tid; i < Q * per; i += NT) {
+            const uint32_t q = i / per, j = i % per, kq = grp * Q + q;
+            if (kq < n_keys)
+                s_cw[q * (CW_WORDS / 4) + j] = reinterpret_cast<const uint4 *>(keys + (size_t)kq * stride + 32)[j];
+        }
+    }
+    // the codewords of key q of the group
+    auto cw_of = [&](uint32_t q) {
+        if constexpr (CWL)
+            return CwLds{(lds_u8 *)(s_cw + q * (CW_WORDS / 4))};
+        else
+            return cw_global(KeyView{keys + (size_t)(grp * Q + q) * stride});
+    };
+
+    expand_top<PRF, Q>(sm, P, cw_of, keys, n_keys, stride, grp, row_base, g, g.lgS, status);
 
     // per-lane depth-first walk of a subtree of height h.  Lane l of wave w
     // evaluates key q = l mod Q over subtree position w P + l / Q (P = 64 / Q
@@ -734,6 +751,198 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
         if (ok == 2)
             v = 0u - v; // party 1 holds the negated share
         atomicAdd(&out[(size_t)(grp * Q + qq) * dim + col], v);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// One key on a large table (above the memory-side cache): the table stream,
+// not the tree, bounds the call, so the waves of a workgroup split the work.
+// Waves 0 .. SP_WAVES-1 (producers) walk the key's subtrees, one lane per
+// subtree as in k_pir_fused, and write each step's leaf shares into an LDS ring
+// of SP_RING steps; the other waves (consumers) stream the table rows of each
+// step from HBM as soon as its shares are in the ring and multiply them in.
+// The consumers carry no tree state, so they keep 16 row loads of 16 bytes
+// in flight per lane whatever the tree work is doing.  The ring's slots are
+// handed over with workgroup-scope counters in LDS: a producer wave adds one
+// to ready[slot] after writing its part of a step, a consumer wave adds one to
+// freed[slot] after its last read of it.  Every wait is bounded: a wait that
+// runs out (which correct code never reaches) sets PIR_STATUS_STALLED and the
+// waves leave their loops, so the kernel always ends.
+// ---------------------------------------------------------------------------
+constexpr uint32_t SP_WAVES = 4;                 // producer waves
+constexpr uint32_t SP_LANES = 64 * SP_WAVES;      // subtrees per workgroup
+constexpr uint32_t SP_LGS = 8;                    // log2 SP_LANES: breadth-first levels
+constexpr uint32_t SP_RING = 4;                   // steps of shares in the ring
+constexpr uint32_t SP_STEP_WORDS = 2 * SP_LANES;  // shares of one step
+constexpr uint32_t SP_CONS = NW - SP_WAVES;       // consumer waves
+constexpr uint32_t SP_ROWS_PER_WAVE = SP_STEP_WORDS / SP_CONS; // rows of a step per consumer wave
+constexpr uint32_t SP_U = 16;                     // row loads in flight per consumer lane
+constexpr uint32_t SPIN_LIMIT = 1u << 22;
+static_assert(SP_RING * SP_STEP_WORDS * 4 <= sizeof(Seed) * NT, "the ring lives in the breadth-first area");
+static_assert(SP_ROWS_PER_WAVE % (4 * SP_U) == 0, "whole rounds of loads per step");
+
+// Waits until the LDS counter reaches target; false if the wait ran out.
+__device__ __forceinline__ bool wait_count(uint32_t *ctr, uint32_t target)
+{
+    for (uint32_t it = 0; it < SPIN_LIMIT; it++) {
+        if (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target)
+            return true;
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return false;
+}
+
+template <class PRF>
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_stream(const uint8_t *__restrict__ keys,
+                                                   const uint32_t *__restrict__ table, uint64_t rows, uint32_t dim,
+                                                   uint32_t *__restrict__ out, Geometry g, uint32_t *status)
+{
+    __shared__ Smem<PRF::TAB_WORDS> sm;
+    constexpr uint32_t CW_WORDS = 64 * PIR_MAX_LOG_DOMAIN / 4;
+    __shared__ uint4 s_cw[CW_WORDS / 4];
+    __shared__ uint32_t ready[SP_RING], freed[SP_RING], stalled;
+
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const uint32_t chunk = xcd_block();
+    const uint64_t row_base = (uint64_t)chunk << g.H;
+    const PRF P(sm.tab, lane);
+    if (tid < SP_RING) {
+        ready[tid] = 0;
+        freed[tid] = 0;
+    }
+    if (tid == 0)
+        stalled = 0;
+    for (uint32_t i = tid; i < 4 * g.n; i += NT)
+        s_cw[i] = reinterpret_cast<const uint4 *>(keys + 32)[i];
+    auto cw_of = [&](uint32_t) { return CwLds{(lds_u8 *)s_cw}; };
+    expand_top<PRF, 1>(sm, P, cw_of, keys, 1, 0, 0, row_base, g, SP_LGS, status);
+    const uint32_t ok = sm.keyok[0];
+    if (!ok)
+        return; // uniform: the output row stays zero
+
+    const uint32_t h = g.H - SP_LGS; // >= 1
+    const uint32_t steps = 1u << (h - 1);
+    const Seed root = wave < SP_WAVES ? sm.u.bfs[tid] : Seed{{0, 0, 0, 0}};
+    __syncthreads(); // every producer has its subtree root: the breadth-first area becomes the ring
+    uint32_t *const ring = reinterpret_cast<uint32_t *>(sm.u.bfs);
+    uint32_t accw[4] = {0, 0, 0, 0};
+
+    if (wave < SP_WAVES) {
+        // producer lane p walks subtree p (rows p 2^h .. of the chunk) depth-first
+        const uint32_t p = tid;
+        const CwLds C = cw_of(0);
+        const uint32_t d0 = g.n - h;
+        const uint64_t lane_row0 = row_base + ((uint64_t)p << h);
+        Seed node = root;
+        Seed right[HMAX];
+#pragma unroll
+        for (int i = 0; i < HMAX; i++)
+            right[i] = Seed{{0, 0, 0, 0}};
+        for (uint32_t m = 0; m < steps; m++) {
+            const uint32_t slot = m % SP_RING;
+            uint32_t kst = 1;
+            if (m != 0) {
+                const uint32_t kf = h - 1 - __builtin_ctz(m);
+#pragma unroll
+                for (int i = 1; i < HMAX; i++)
+                    if ((uint32_t)i == kf)
+                        node = right[i];
+                kst = kf + 1;
+            }
+            for (uint32_t k = kst; k < h; k++) {
+                Seed c0, c1;
+                children(P, C, node, d0 + k, c0, c1);
+#pragma unroll
+                for (int i = 1; i < HMAX; i++)
+                    if ((uint32_t)i == k)
+                        right[i] = c1;
+                node = c0;
+            }
+            const uint2 cw = C.cw_word0(g.n, node.w[0] & 1u);
+            uint32_t y0, y1;
+            P.pair_word0(node.w, y0, y1);
+            const uint64_t r0 = lane_row0 + 2 * m;
+            y0 = r0 < rows ? y0 ^ cw.x : 0u; // rows past the table add nothing
+            y1 = r0 + 1 < rows ? y1 ^ cw.y : 0u;
+            // the slot is free once every consumer wave is done with step m - SP_RING
+            if (m >= SP_RING && !wait_count(&freed[slot], SP_CONS * (m / SP_RING))) {
+                stalled = 1;
+                break;
+            }
+            ring[slot * SP_STEP_WORDS + 2 * p] = y0;
+            ring[slot * SP_STEP_WORDS + 2 * p + 1] = y1;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0)
+                __hip_atomic_fetch_add(&ready[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    } else {
+        // consumer wave c takes rows c R .. (c + 1) R - 1 of each step (R =
+        // SP_ROWS_PER_WAVE; step row k is leaf k mod 2 of subtree k / 2);
+        // lane (rs = lane / 16, cg = lane mod 16) loads 16 bytes, columns
+        // 4 cg .. 4 cg + 3, of every fourth of them
+        const uint32_t c = wave - SP_WAVES, rs = lane >> 4, cg = lane & 15, col = 4 * cg;
+        const bool col_ok = col < dim;
+#pragma unroll 1
+        for (uint32_t m = 0; m < steps; m++) {
+            const uint32_t slot = m % SP_RING;
+            // issue the step's first round of loads before waiting for its shares
+            uint4 tv[SP_U];
+            auto load_round = [&](uint32_t r0) {
+#pragma unroll
+                for (uint32_t u = 0; u < SP_U; u++) {
+                    const uint32_t k = c * SP_ROWS_PER_WAVE + r0 + 4 * u + rs;
+                    const uint64_t row = row_base + ((uint64_t)(k >> 1) << h) + 2 * m + (k & 1);
+                    const uint32_t *trow = table + (row < rows ? row : rows - 1) * dim;
+                    tv[u] = col_ok ? row_load4<true>(trow + col) : make_uint4(0, 0, 0, 0);
+                }
+            };
+            load_round(0);
+            if (!wait_count(&ready[slot], SP_WAVES * (m / SP_RING + 1))) {
+                stalled = 1;
+                break;
+            }
+            const uint32_t *sh = ring + slot * SP_STEP_WORDS + c * SP_ROWS_PER_WAVE + rs;
+#pragma unroll 1 // one round of loads in flight: unrolled, the rounds' loads all hoist and spill
+            for (uint32_t r0 = 0; r0 < SP_ROWS_PER_WAVE; r0 += 4 * SP_U) {
+                if (r0)
+                    load_round(r0);
+#pragma unroll
+                for (uint32_t u = 0; u < SP_U; u++) {
+                    const uint32_t y = sh[r0 + 4 * u]; // zero for rows past the table
+                    accw[0] += y * tv[u].x;
+                    accw[1] += y * tv[u].y;
+                    accw[2] += y * tv[u].z;
+                    accw[3] += y * tv[u].w;
+                }
+            }
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (lane == 0)
+                __hip_atomic_fetch_add(&freed[slot], 1u, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        }
+    }
+
+    // the consumers' sums per column, reduced in LDS (the tables are no longer needed)
+    __syncthreads();
+    uint32_t *s_acc = sm.tab;
+    for (uint32_t i = tid; i < dim; i += NT)
+        s_acc[i] = 0;
+    __syncthreads();
+    if (wave >= SP_WAVES) {
+#pragma unroll
+        for (int e = 0; e < 4; e++) {
+            const uint32_t cc = 4 * (lane & 15) + e;
+            if (cc < dim)
+                atomicAdd(&s_acc[cc], accw[e]);
+        }
+    }
+    __syncthreads();
+    if (tid == 0 && stalled)
+        atomicOr(status, PIR_STATUS_STALLED);
+    for (uint32_t i = tid; i < dim; i += NT) {
+        uint32_t v = s_acc[i];
+        if (ok == 2)
+            v = 0u - v; // party 1 holds the negated share
+        atomicAdd(&out[i], v);
     }
 }
 

@@ -30,7 +30,7 @@ PLAN_MODEL, PLAN_TUNED = 0, 1
 TUNE_MODEL = 0xFFFFFFFF
 WORKSPACE_BYTES = 256
 STATUS_BAD_KEY = 1
-KERNEL_WAVES, KERNEL_SMALL_BATCH = 1, 2
+KERNEL_WAVES, KERNEL_SMALL_BATCH, KERNEL_STREAM = 1, 2, 3
 BINS_MIN_LOG, BINS_MAX_DIM = 3, 128
 
 _lib = None

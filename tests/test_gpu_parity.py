@@ -19,11 +19,11 @@ def oracle_keys(O, n, alphas, seed):
     return O.gen_batch(n, alphas, seeds)
 
 
-def gpu_answer(pir, keys_np, table_dev):
+def gpu_answer(pir, keys_np, table_dev, prf=0):
     import torch
 
     keys = torch.from_numpy(np.ascontiguousarray(keys_np)).cuda()
-    out = pir.answer(keys, table_dev)
+    out = pir.answer(keys, table_dev, prf=prf)
     torch.cuda.synchronize()
     return out.cpu().numpy().view(np.uint32)
 
@@ -790,3 +790,63 @@ def test_table_at_a_4_byte_offset(O, pirmod, prf, rows, dim, nkeys):
     torch.cuda.synchronize()
     for v in views:
         assert (v.cpu().numpy().view(np.uint32) == want).all()
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+@pytest.mark.parametrize("rows,dim", [(1 << 21, 64), ((1 << 22) + 12345, 40), (1 << 23, 16)])
+def test_single_key_stream_kernel_dense(O, pirmod, prf, rows, dim):
+    """One key on a table above 256 MiB with rows of at most 64 words: with
+    AES-128 it runs on k_pir_stream (tree waves and table-stream waves), with
+    ChaCha20 on k_pir_fused; both parties' answers against the full oracle,
+    and the reconstruction, on dense tables (one of them ragged)."""
+    import torch
+
+    want_kernel = pirmod.KERNEL_STREAM if prf == 0 else pirmod.KERNEL_SMALL_BATCH
+    assert pirmod.plan(1, rows, dim, prf=prf)["kernel"] == want_kernel
+    seed = rows % 1000 + dim + prf
+    n = log_domain(rows)
+    T = W.make_table(rows, dim, seed)
+    Tn = T.numpy().view(np.uint32)
+    Td = T.cuda()
+    a = W.uniform_indices(rows, 1, seed)
+    K0, K1 = O.gen_batch(n, a, W.key_seeds(1, seed), prf_id=prf)
+    g0 = gpu_answer(pirmod, K0, Td, prf)
+    g1 = gpu_answer(pirmod, K1, Td, prf)
+    assert pirmod.check_status() == pirmod.PIR_OK
+    assert (g0 == O.answer_batch(K0, Tn, nthreads=cpu_threads())).all()
+    assert (g1 == O.answer_batch(K1, Tn, nthreads=cpu_threads())).all()
+    assert (O.reconstruct(g0[0], g1[0]) == Tn[a[0]]).all()
+    bad = K0.copy()
+    bad[0, 2] = n + 1  # wrong domain: zero row, status
+    assert (gpu_answer(pirmod, bad, Td, prf) == 0).all()
+    assert pirmod.check_status() == pirmod.PIR_EKEY
+    del Td
+    torch.cuda.empty_cache()
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+def test_single_key_stream_kernel_2p25_and_a_slice(O, pirmod, prf):
+    """One key on the 2^25 x 64 table (sparse copy, per server against point
+    evaluation) and on a 2^23-row slice of it at row 3 * 2^23
+    (pir_answer_slice, per server against point evaluation of the slice's
+    indices): the stream kernel with AES-128, k_pir_fused with ChaCha20."""
+    import torch
+
+    rows, dim, seed = 1 << 25, 64, 70 + prf
+    Ts, sup, vals = make_sparse(rows, dim, seed, 24, "cuda")
+    a = [int(sup[5])]  # a queried row in the support
+    K0, K1 = O.gen_batch(25, a, W.key_seeds(1, seed), prf_id=prf)
+    g0, g1 = gpu_answer(pirmod, K0, Ts, prf), gpu_answer(pirmod, K1, Ts, prf)
+    assert (g0 == sparse_answers(O, K0, sup, vals)).all() and (g1 == sparse_answers(O, K1, sup, vals)).all()
+    assert (O.reconstruct(g0[0], g1[0]) == vals[5]).all()
+    # a slice holding indices 3 * 2^23 .. 4 * 2^23 - 1
+    size, row0 = 1 << 23, 3 << 23
+    keep = (sup >= row0) & (sup < row0 + size)
+    assert keep.any()
+    sl = Ts[row0:row0 + size].contiguous()
+    out = pirmod.answer_slice(torch.from_numpy(K0).cuda(), sl, 25, row0, prf=prf)
+    torch.cuda.synchronize()
+    want = sparse_answers(O, K0, sup[keep], vals[keep])
+    assert (out.cpu().numpy().view(np.uint32) == want).all()
+    del Ts, sl
+    torch.cuda.empty_cache()

@@ -241,14 +241,26 @@ def test_plan_batched_default_workload():
 
 
 def test_plan_single_key_spreads_over_every_cu():
-    """One key on 2^20 rows: the small-batch kernel with about two workgroups
-    per CU of the 256, each covering its own rows."""
+    """One key: about two workgroups per CU of the 256, each covering its own
+    rows; the small-batch kernel up to 256 MiB of table, above it with
+    AES-128 the stream kernel (256 tree lanes per workgroup: 8 breadth-first
+    levels) while its subtree height fits the path registers."""
     for rows in (1 << 20, 1 << 22, 1 << 25, 1 << 32):
-        p = pir.plan(1, rows, 64)
-        assert p["kernel"] == pir.KERNEL_SMALL_BATCH
-        assert p["workgroups"] >= 2 * 256, (rows, p)
-        assert p["workgroups"] * p["rows_per_item"] >= rows
-        assert p["descent_levels"] + p["bfs_levels"] + p["subtree_log"] == p["n"]
+        for prf in ("aes128", "chacha20"):
+            p = pir.plan(1, rows, 64, prf=prf)
+            stream = prf == "aes128" and 1 << 20 < rows < 1 << 32
+            assert p["kernel"] == (pir.KERNEL_STREAM if stream else pir.KERNEL_SMALL_BATCH), (rows, prf, p)
+            assert p["bfs_levels"] == (8 if stream else 9)
+            assert p["workgroups"] >= 2 * 256, (rows, p)
+            assert p["workgroups"] * p["rows_per_item"] >= rows
+            assert p["descent_levels"] + p["bfs_levels"] + p["subtree_log"] == p["n"]
+    # rows of 16, 32 or 64 words stream; wider rows and tables up to 256 MiB do not
+    assert pir.plan(1, 1 << 23, 16)["kernel"] == pir.KERNEL_STREAM
+    assert pir.plan(1, 1 << 22, 32)["kernel"] == pir.KERNEL_STREAM
+    assert pir.plan(1, 1 << 22, 100)["kernel"] == pir.KERNEL_SMALL_BATCH
+    assert pir.plan(1, 1 << 22, 63)["kernel"] == pir.KERNEL_SMALL_BATCH
+    assert pir.plan(1, 1 << 22, 16)["kernel"] == pir.KERNEL_SMALL_BATCH  # 256 MiB
+    assert pir.plan(2, 1 << 25, 64)["kernel"] == pir.KERNEL_SMALL_BATCH
 
 
 def test_plan_small_wave_batches_fill_the_gpu():
