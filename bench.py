@@ -262,7 +262,7 @@ def main():
                     help="skip the measured peaks (libpir_engine.so probes) in the default line")
     ap.add_argument("--mode", default="batch",
                     choices=["batch", "small", "multi", "large", "serve", "pbr", "hotfull", "sizes", "batchsweep",
-                             "shards"],
+                             "shards", "prf"],
                     help="batch: 2^20 x 64, 512 pairs (the default line); small: 2^14 x 16, one pair; "
                          "multi: 8 tables 2^16..2^23 x 32, ragged Zipf batches in one call; "
                          "large: 2^25 x 64 (8 GiB), 512..2048 pairs; serve: Poisson request loop over 4 tables; "
@@ -270,7 +270,8 @@ def main():
                          "hotfull: hot table + full table with fixed query budgets; "
                          "sizes: 2^14, 2^20, 2^22 rows x 64 (the table sizes of the paper's GPU/CPU comparison); "
                          "batchsweep: latency and throughput for 1..1024 keys per call on 2^20 x 64; "
-                         "shards: one GPU's share of the 2^25 x 64 table split over 2, 4, 8 GPUs (row slices)")
+                         "shards: one GPU's share of the 2^25 x 64 table split over 2, 4, 8 GPUs (row slices); "
+                         "prf: tree nodes/s of the PRF codes alone (AES-128 T-table and bitsliced, ChaCha20)")
     ap.add_argument("--plans", default="tuned", choices=["tuned", "model"],
                     help="tuned: the autotuner's cache for this system where it applies (default); "
                          "model: the library's cost model only")
@@ -562,6 +563,8 @@ def engine_lib(what: str):
     lib.pir_prf_engine.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                    ctypes.c_void_p]
     lib.pir_prf_engine.restype = ctypes.c_int
+    lib.pir_prf_engine_lanes.argtypes = [ctypes.c_uint32]
+    lib.pir_prf_engine_lanes.restype = ctypes.c_uint32
     lib.pir_peak_probe.argtypes = [ctypes.c_uint32, ctypes.c_uint32, ctypes.c_uint32, ctypes.c_void_p,
                                    ctypes.c_uint64, ctypes.c_void_p, ctypes.c_void_p]
     lib.pir_peak_probe.restype = ctypes.c_int
@@ -656,6 +659,54 @@ def prf_engine_rate(prf: str, kernel_nodes_per_s: float) -> dict | None:
     return {"engine_nodes_per_s": round(nodes_s, 1), "kernel_nodes_per_s": round(kernel_nodes_per_s, 1),
             "frac": round(kernel_nodes_per_s / nodes_s, 4),
             "engine": "k_prf_engine: 2048 x 512 lanes, 512 steps of one full and one bottom node each"}
+
+
+# PRF engines (libpir_engine.so, pir_prf_engine): kind -> (name, workgroups,
+# steps per lane, tree nodes one lane-step counts for)
+PRF_ENGINES = {
+    0: ("aes128_ttable_walk", 2048, 512, 2),        # one full and one bottom node
+    2: ("aes128_ttable_full", 2048, 256, 1),        # one full node
+    3: ("aes128_bitsliced_full", 1536, 32, 8),      # 32 full nodes per quad of lanes
+    1: ("chacha20_walk", 2048, 512, 2),
+}
+
+
+def prf_sweep(args):
+    """Tree nodes per second of each PRF code alone, node for node: the
+    T-table AES-128 rounds (as the walk mixes full and bottom nodes, and full
+    nodes only), the bitsliced AES-128 rounds (full nodes only: a quad of
+    lanes evaluates 32 nodes per step, no LDS), and ChaCha20.  Median of 5
+    timed launches after one warm-up."""
+    import ctypes
+
+    import torch
+
+    lib = engine_lib("prf mode")
+    if lib is None:
+        raise SystemExit("prf mode needs libpir_engine.so")
+    stream = torch.cuda.current_stream()
+    res = {}
+    for kind, (name, blocks, steps, per_step) in PRF_ENGINES.items():
+        lanes = lib.pir_prf_engine_lanes(kind)
+        out = torch.zeros(blocks * lanes, dtype=torch.int32, device="cuda")
+
+        def run():
+            rc = lib.pir_prf_engine(kind, blocks, steps, ctypes.c_void_p(out.data_ptr()),
+                                    ctypes.c_void_p(stream.cuda_stream))
+            if rc != 0:
+                raise RuntimeError(f"pir_prf_engine({kind}) failed: {rc}")
+
+        _, ms = time_launches(run, 5, 1)
+        med = float(np.median(ms))
+        nodes = blocks * lanes * steps * per_step
+        res[name] = {"nodes_per_s": round(nodes / (med * 1e-3), 1), "ms": round(med, 4), "nodes": nodes,
+                     "workgroups": blocks, "lanes_per_workgroup": lanes, "steps": steps,
+                     "checksum_nonzero": bool(out.ne(0).any().item())}
+    tt, bs = res["aes128_ttable_full"]["nodes_per_s"], res["aes128_bitsliced_full"]["nodes_per_s"]
+    return {"value": round(bs, 1), "unit": "tree nodes/s (bitsliced AES-128, full nodes)",
+            "engines": res, "bitsliced_vs_ttable_full": round(bs / tt, 4),
+            "config": {"workload": "PRF engines alone: chains of GGM tree nodes (AES-128 keyed by the seed, "
+                                   "counter blocks 0 and 1), no codewords, table or contraction"}}
 
 
 def time_launches(fn, steps, warmup):
@@ -784,6 +835,8 @@ def other_modes(args):
         line.update(batch_sweep(args))
     elif args.mode == "hotfull":
         line.update(hotfull_run(args))
+    elif args.mode == "prf":
+        line.update(prf_sweep(args))
     else:
         line.update(serve_sweep(args))
     print(json.dumps(line), flush=True)

@@ -51,3 +51,27 @@ def test_tree_kernels_keep_their_lds_tables(device_asm):
     for name, (lds, scratch) in chacha.items():
         assert lds < 65536, f"{name}: LDS {lds} bytes; ChaCha20 needs no table"
         assert scratch <= 64, f"{name}: {scratch} bytes of scratch per lane"
+
+
+def test_bitsliced_prf_engine_builds_without_scratch():
+    """The bitsliced AES-128 engine (measurement library) compiles, which runs
+    its compile-time checks of the tower-field S-box circuit against the
+    FIPS-197 S-box on all 256 bytes and of the bit transpose, and keeps its 96
+    state planes in registers: no scratch and no LDS."""
+    hipcc = pbuild.hipcc()
+    if not shutil.which(hipcc):
+        pytest.skip("hipcc not available")
+    import tempfile
+    from pathlib import Path
+
+    flags = [f for f in pbuild.HIPCC_FLAGS if f not in ("-shared", "-fPIC")]
+    with tempfile.TemporaryDirectory() as d:
+        out = Path(d) / "prf_engine.s"
+        subprocess.run([hipcc, *flags, f"-I{pbuild.ROOT / 'include'}", f"-I{pbuild.CSRC}",
+                        "--cuda-device-only", "-S", str(pbuild.CSRC / "prf_engine.hip"), "-o", str(out)],
+                       check=True, capture_output=True)
+        meta = kernel_metadata(out.read_text())
+    bs = {k: v for k, v in meta.items() if "bitsliced" in k}
+    assert len(bs) == 2, sorted(meta)
+    for name, (lds, scratch) in bs.items():
+        assert lds == 0 and scratch == 0, (name, lds, scratch)

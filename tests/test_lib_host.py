@@ -391,8 +391,18 @@ def test_prf_engine_library_exports_and_rejects_bad_arguments():
                                    ctypes.c_void_p]
     eng.pir_prf_engine.restype = ctypes.c_int
     assert eng.pir_prf_engine(0, 1, 1, None, None) == -1        # no output buffer
-    assert eng.pir_prf_engine(2, 1, 1, ctypes.c_void_p(16), None) == -1  # unknown PRF
+    assert eng.pir_prf_engine(4, 1, 1, ctypes.c_void_p(16), None) == -1  # unknown engine
     assert eng.pir_prf_engine(0, 0, 1, ctypes.c_void_p(16), None) == -1  # no workgroups
+    eng.pir_prf_engine_lanes.argtypes = [ctypes.c_uint32]
+    eng.pir_prf_engine_lanes.restype = ctypes.c_uint32
+    assert [eng.pir_prf_engine_lanes(k) for k in range(5)] == [512, 512, 512, 256, 0]
+    f = eng.pir_prf_bitsliced_pairs
+    f.argtypes = [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p]
+    f.restype = ctypes.c_int
+    assert f(None, 32, ctypes.c_void_p(16), None) == -1               # no seeds
+    assert f(ctypes.c_void_p(16), 32, None, None) == -1               # no output
+    assert f(ctypes.c_void_p(16), (1 << 26) + 1, ctypes.c_void_p(16), None) == -1  # too many seeds
+    assert f(None, 0, None, None) == 0                                # nothing to do
 
 
 def test_peak_probes_export_and_reject_bad_arguments():
