@@ -58,6 +58,7 @@ extern "C" {
 #define PIR_ENOMEM (-2) /* a size beyond what the library supports          */
 #define PIR_EHIP (-3)   /* a HIP runtime call or kernel launch failed       */
 #define PIR_EKEY (-4)   /* a device-resident key had a bad header           */
+#define PIR_ESTALL (-5) /* a kernel gave up a bounded wait: output invalid  */
 
 #define PIR_KEY_VERSION 1
 #define PIR_MAX_LOG_DOMAIN 32 /* n <= 32: tables of at most 2^32 rows */
@@ -321,6 +322,7 @@ int pir_reconstruct(const uint32_t *a0, const uint32_t *a1, uint32_t dim, uint32
 #define PIR_STATUS_BAD_KEY 1u     /* status bit: a key had a bad header */
 #define PIR_STATUS_STALLED 2u     /* status bit: a kernel gave up a bounded wait (never expected;
                                      the call's output is then not valid) */
+#define PIR_WAIT_LIMIT_DEFAULT (1u << 22) /* tries of a bounded wait (see pir_set_wait_limit) */
 
 /* Bytes of a status workspace: PIR_WORKSPACE_BYTES. */
 size_t pir_workspace_size(void);
@@ -335,15 +337,25 @@ int pir_set_workspace(void *d_ws, size_t bytes);
 
 /* The status of the last call that used workspace d_ws, in the order of
  * `stream`: enqueues a read of the word on `stream` and waits for it, so the
- * calls enqueued on `stream` before have completed.  PIR_EKEY if that call
- * saw a key with a bad header (version, party, n or PRF id), else PIR_OK;
- * PIR_EINVAL for a null or misaligned d_ws; PIR_EHIP if the read fails. */
+ * calls enqueued on `stream` before have completed.  PIR_ESTALL if one of
+ * that call's kernels gave up a bounded wait (its output is not valid), else
+ * PIR_EKEY if it saw a key with a bad header (version, party, n or PRF id),
+ * else PIR_OK; PIR_EINVAL for a null or misaligned d_ws; PIR_EHIP if the read
+ * fails. */
 int pir_workspace_status(const void *d_ws, void *stream);
 
 /* After the caller has synchronised the stream of the last call that used the
- * library's own workspace on the current device: PIR_EKEY if that call saw a
- * key with a bad header, else PIR_OK; PIR_EHIP if the word cannot be read. */
+ * library's own workspace on the current device: PIR_ESTALL, PIR_EKEY or
+ * PIR_OK as for pir_workspace_status; PIR_EHIP if the word cannot be read. */
 int pir_check_status(void);
+
+/* The number of tries a kernel's bounded wait makes before it gives up
+ * (waves of one workgroup handing work to each other; a wait that gives up
+ * sets PIR_STATUS_STALLED and the kernel ends).  Correct code never reaches
+ * the default, PIR_WAIT_LIMIT_DEFAULT; tests of the stalled-wait path set a
+ * small limit to force it, and 0 restores the default.  Applies to calls
+ * launched afterwards from any thread.  Returns PIR_OK. */
+int pir_set_wait_limit(uint32_t tries);
 
 /* Static, NUL-terminated description of a status code. */
 const char *pir_strerror(int status);

@@ -29,6 +29,9 @@ static uint32_t ceil_log2(uint64_t x)
 // instantiations that read single words.
 static bool vec_aligned(const uint32_t *d_table) { return (uintptr_t)d_table % 16 == 0; }
 
+// tries of a kernel's bounded wait (pir_set_wait_limit)
+static std::atomic<uint32_t> g_wait_limit{PIR_WAIT_LIMIT_DEFAULT};
+
 template <class PRF, int Q>
 static void launch_q(uint32_t kch, dim3 grid, hipStream_t st, const uint8_t *keys, uint32_t n_keys,
                      uint32_t stride, const uint32_t *table, uint64_t rows, uint32_t dim, uint32_t *out,
@@ -44,14 +47,14 @@ static void launch_q(uint32_t kch, dim3 grid, hipStream_t st, const uint8_t *key
         // the caches (measured with AES-128: 2^22 x 64 0.235 -> 0.215 ms, 2^25
         // x 64 1.48 -> 1.44 ms; at 2^20 x 64, 256 MiB, cached reads are faster)
         if (v4 && rows * dim * 4ull > (256ull << 20)) {
-            if (kch == 1 && PRF::TAB_WORDS && g.H > SP_LGS && g.H <= SP_LGS + HMAX) {
-                // rows of up to 64 words, AES-128: tree waves and table-stream
+            if (kch == 1 && PRF::TAB_WORDS && n_keys == 1 && g.H > SP_LGS && g.H <= SP_LGS + HMAX) {
+                // one key, rows of up to 64 words, AES-128: tree waves and table-stream
                 // waves (k_pir_stream; measured, 1 key: 2^25 x 64 1.476 ->
                 // 1.404 ms, 2^22 x 64 0.224 -> 0.206, 2^24 x 32 0.625 -> 0.587,
                 // 2^23 x 16 0.309 -> 0.281).  ChaCha20 keeps k_pir_fused, where
                 // the split gained nothing (2^25 x 64 1.541 against 1.568 ms)
                 hipLaunchKernelGGL((k_pir_stream<PRF>), grid, dim3(NT), 0, st, keys, table, rows, dim, out, g,
-                                   status);
+                                   status, g_wait_limit.load(std::memory_order_relaxed));
                 return;
             }
             if (kch == 1)
@@ -745,7 +748,7 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
     out->items = p.grid;
     out->workgroups = p.grid;
     out->lanes_per_workgroup = NT;
-    if (aes && p.Q == 1 && p.kch == 1 && dim % 4 == 0 && rows * dim * 4ull > (256ull << 20) &&
+    if (aes && p.Q == 1 && n_keys == 1 && p.kch == 1 && dim % 4 == 0 && rows * dim * 4ull > (256ull << 20) &&
         p.g.H > SP_LGS && p.g.H <= SP_LGS + HMAX) { // (for a 16-byte aligned table)
         out->kernel = PIR_KERNEL_STREAM;
         out->lds_bytes = (uint32_t)sizeof(Smem<AesPrf::TAB_WORDS>) + 64 * PIR_MAX_LOG_DOMAIN;
@@ -881,6 +884,17 @@ int pir_answer_multi(const pir_table_t *tables, uint32_t n_tables, const uint8_t
     return pir_answer_multi_prf(PIR_PRF_AES128, tables, n_tables, d_keys, key_stride, d_out, stream);
 }
 
+} // extern "C"
+
+// The status code of a status word: a stalled wait first (the output is not
+// valid), then a bad key.
+static int status_code(uint32_t v)
+{
+    return (v & PIR_STATUS_STALLED) ? PIR_ESTALL : (v & PIR_STATUS_BAD_KEY) ? PIR_EKEY : PIR_OK;
+}
+
+extern "C" {
+
 int pir_check_status(void)
 {
     uint32_t *p = default_workspace();
@@ -890,7 +904,13 @@ int pir_check_status(void)
     const hipError_t e = hipMemcpy(&v, p, sizeof v, hipMemcpyDeviceToHost);
     if (e != hipSuccess)
         return fail_hip(e);
-    return (v & PIR_STATUS_BAD_KEY) ? PIR_EKEY : PIR_OK;
+    return status_code(v);
+}
+
+int pir_set_wait_limit(uint32_t tries)
+{
+    g_wait_limit.store(tries ? tries : PIR_WAIT_LIMIT_DEFAULT, std::memory_order_relaxed);
+    return PIR_OK;
 }
 
 size_t pir_workspace_size(void) { return PIR_WORKSPACE_BYTES; }
@@ -914,7 +934,7 @@ int pir_workspace_status(const void *d_ws, void *stream)
         e = hipStreamSynchronize(st);
     if (e != hipSuccess)
         return fail_hip(e);
-    return (v & PIR_STATUS_BAD_KEY) ? PIR_EKEY : PIR_OK;
+    return status_code(v);
 }
 
 } // extern "C"

@@ -244,6 +244,8 @@ const char *pir_strerror(int status)
         return "HIP runtime error";
     case PIR_EKEY:
         return "a key had a bad header";
+    case PIR_ESTALL:
+        return "a kernel gave up a bounded wait (the output is not valid)";
     default:
         return "unknown status";
     }

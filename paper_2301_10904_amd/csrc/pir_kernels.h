@@ -765,9 +765,9 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
 // in flight per lane whatever the tree work is doing.  The ring's slots are
 // handed over with workgroup-scope counters in LDS: a producer wave adds one
 // to ready[slot] after writing its part of a step, a consumer wave adds one to
-// freed[slot] after its last read of it.  Every wait is bounded: a wait that
-// runs out (which correct code never reaches) sets PIR_STATUS_STALLED and the
-// waves leave their loops, so the kernel always ends.
+// freed[slot] after its last read of it.  Every wait is bounded (wait_limit
+// tries): a wait that runs out (which correct code never reaches) sets
+// PIR_STATUS_STALLED and the waves leave their loops, so the kernel always ends.
 // ---------------------------------------------------------------------------
 constexpr uint32_t SP_WAVES = 4;                 // producer waves
 constexpr uint32_t SP_LANES = 64 * SP_WAVES;      // subtrees per workgroup
@@ -777,14 +777,14 @@ constexpr uint32_t SP_STEP_WORDS = 2 * SP_LANES;  // shares of one step
 constexpr uint32_t SP_CONS = NW - SP_WAVES;       // consumer waves
 constexpr uint32_t SP_ROWS_PER_WAVE = SP_STEP_WORDS / SP_CONS; // rows of a step per consumer wave
 constexpr uint32_t SP_U = 16;                     // row loads in flight per consumer lane
-constexpr uint32_t SPIN_LIMIT = 1u << 22;
 static_assert(SP_RING * SP_STEP_WORDS * 4 <= sizeof(Seed) * NT, "the ring lives in the breadth-first area");
 static_assert(SP_ROWS_PER_WAVE % (4 * SP_U) == 0, "whole rounds of loads per step");
 
-// Waits until the LDS counter reaches target; false if the wait ran out.
-__device__ __forceinline__ bool wait_count(uint32_t *ctr, uint32_t target)
+// Waits until the LDS counter reaches target, for at most `limit` tries;
+// false if the wait ran out.
+__device__ __forceinline__ bool wait_count(uint32_t *ctr, uint32_t target, uint32_t limit)
 {
-    for (uint32_t it = 0; it < SPIN_LIMIT; it++) {
+    for (uint32_t it = 0; it < limit; it++) {
         if (__hip_atomic_load(ctr, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) >= target)
             return true;
         __builtin_amdgcn_s_sleep(1);
@@ -795,7 +795,8 @@ __device__ __forceinline__ bool wait_count(uint32_t *ctr, uint32_t target)
 template <class PRF>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_stream(const uint8_t *__restrict__ keys,
                                                    const uint32_t *__restrict__ table, uint64_t rows, uint32_t dim,
-                                                   uint32_t *__restrict__ out, Geometry g, uint32_t *status)
+                                                   uint32_t *__restrict__ out, Geometry g, uint32_t *status,
+                                                   uint32_t wait_limit)
 {
     __shared__ Smem<PRF::TAB_WORDS> sm;
     constexpr uint32_t CW_WORDS = 64 * PIR_MAX_LOG_DOMAIN / 4;
@@ -865,7 +866,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
             y0 = r0 < rows ? y0 ^ cw.x : 0u; // rows past the table add nothing
             y1 = r0 + 1 < rows ? y1 ^ cw.y : 0u;
             // the slot is free once every consumer wave is done with step m - SP_RING
-            if (m >= SP_RING && !wait_count(&freed[slot], SP_CONS * (m / SP_RING))) {
+            if (m >= SP_RING && !wait_count(&freed[slot], SP_CONS * (m / SP_RING), wait_limit)) {
                 stalled = 1;
                 break;
             }
@@ -897,7 +898,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                 }
             };
             load_round(0);
-            if (!wait_count(&ready[slot], SP_WAVES * (m / SP_RING + 1))) {
+            if (!wait_count(&ready[slot], SP_WAVES * (m / SP_RING + 1), wait_limit)) {
                 stalled = 1;
                 break;
             }

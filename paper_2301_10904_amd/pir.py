@@ -15,7 +15,7 @@ import numpy as np
 PKG = Path(__file__).resolve().parent
 LIB_PATH = PKG / "libpir.so"
 
-PIR_OK, PIR_EINVAL, PIR_ENOMEM, PIR_EHIP, PIR_EKEY = 0, -1, -2, -3, -4
+PIR_OK, PIR_EINVAL, PIR_ENOMEM, PIR_EHIP, PIR_EKEY, PIR_ESTALL = 0, -1, -2, -3, -4, -5
 MAX_DIM = 256
 PRF_AES128, PRF_CHACHA20 = 0, 1  # key byte 3
 PRFS = {"aes128": PRF_AES128, "chacha20": PRF_CHACHA20}
@@ -25,11 +25,12 @@ EXPORTS = ("dpf_key_size", "dpf_gen", "dpf_gen_prf", "pir_answer", "pir_answer_p
            "pir_answer_multi", "pir_answer_multi_prf", "pir_answer_bins", "pir_plan", "pir_plan_bins",
            "pir_reconstruct", "pir_workspace_size", "pir_set_workspace", "pir_workspace_status",
            "pir_check_status", "pir_strerror", "pir_last_hip_error", "pir_set_tuning", "pir_tuning_count",
-           "pir_kernel_digest")
+           "pir_kernel_digest", "pir_set_wait_limit")
 PLAN_MODEL, PLAN_TUNED = 0, 1
 TUNE_MODEL = 0xFFFFFFFF
 WORKSPACE_BYTES = 256
-STATUS_BAD_KEY = 1
+STATUS_BAD_KEY, STATUS_STALLED = 1, 2
+WAIT_LIMIT_DEFAULT = 1 << 22
 KERNEL_WAVES, KERNEL_SMALL_BATCH, KERNEL_STREAM = 1, 2, 3
 BINS_MIN_LOG, BINS_MAX_DIM = 3, 128
 
@@ -139,6 +140,8 @@ def load(path: Path | None = None):
     lib.pir_strerror.argtypes = [ctypes.c_int]
     lib.pir_last_hip_error.restype = ctypes.c_int
     lib.pir_last_hip_error.argtypes = []
+    lib.pir_set_wait_limit.restype = ctypes.c_int
+    lib.pir_set_wait_limit.argtypes = [ctypes.c_uint32]
     if path is None:
         _lib = lib
     return lib
@@ -406,9 +409,16 @@ def reconstruct(a0: np.ndarray, a1: np.ndarray) -> np.ndarray:
 
 def check_status() -> int:
     """Status of the last call that used the library's own workspace on the
-    current device (after the caller has synchronised): PIR_OK, or PIR_EKEY if
-    it saw a key with a bad header."""
+    current device (after the caller has synchronised): PIR_OK, PIR_EKEY if it
+    saw a key with a bad header, PIR_ESTALL if a kernel gave up a bounded wait
+    (its output is then not valid)."""
     return int(load().pir_check_status())
+
+
+def set_wait_limit(tries: int) -> None:
+    """Tries of a kernel's bounded wait before it gives up (0: the default,
+    WAIT_LIMIT_DEFAULT); a small limit forces the stalled-wait path in tests."""
+    _check(load().pir_set_wait_limit(int(tries)), "pir_set_wait_limit")
 
 
 def workspace(device=None):
@@ -434,7 +444,8 @@ def set_workspace(ws) -> None:
 
 def workspace_status(ws, stream=None) -> int:
     """Status of the last call that used workspace `ws`, read in the order of
-    `stream` (waits for the calls enqueued on it): PIR_OK or PIR_EKEY."""
+    `stream` (waits for the calls enqueued on it): PIR_OK, PIR_EKEY or
+    PIR_ESTALL, as check_status()."""
     import torch
 
     _check_dev(ws, "workspace", (torch.uint8,))

@@ -279,3 +279,43 @@ def test_one_key_call_replays_in_a_graph(O, pirmod):
         other = pirmod.answer(torch.from_numpy(sets[2]).cuda(), Td)  # eager work on the library's workspace
         torch.cuda.synchronize()
         assert (other.cpu().numpy().view(np.uint32) == O.answer_batch(sets[2], Tn, nthreads=cpu_threads())).all()
+
+
+def test_a_stalled_wait_is_reported_and_the_kernel_ends(O, pirmod):
+    """The stream kernel's bounded waits forced to give up from the host (a
+    wait limit of one try): every wave leaves its loop, the kernel ends, and
+    the call reports PIR_ESTALL, in a bound workspace and in the library's
+    own; with the default limit restored the same keys answer exactly and
+    report PIR_OK."""
+    import torch
+
+    rows, dim = 1 << 22, 64
+    assert pirmod.plan(1, rows, dim)["kernel"] == pirmod.KERNEL_STREAM
+    Td = W.make_table(rows, dim, 41, device="cuda")
+    a = W.uniform_indices(rows, 1, 41)
+    K0, K1 = O.gen_batch(22, a, W.key_seeds(1, 41), prf_id=0)
+    k0, k1 = torch.from_numpy(K0).cuda(), torch.from_numpy(K1).cuda()
+    ws = pirmod.workspace()
+    try:
+        pirmod.set_wait_limit(1)
+        pirmod.set_workspace(ws)
+        pirmod.answer(k0, Td)
+        assert pirmod.workspace_status(ws) == pirmod.PIR_ESTALL
+        pirmod.set_workspace(None)
+        pirmod.answer(k1, Td)
+        torch.cuda.synchronize()
+        assert pirmod.check_status() == pirmod.PIR_ESTALL
+    finally:
+        pirmod.set_wait_limit(0)
+        pirmod.set_workspace(None)
+    pirmod.set_workspace(ws)
+    try:
+        o0 = pirmod.answer(k0, Td)
+        assert pirmod.workspace_status(ws) == pirmod.PIR_OK
+    finally:
+        pirmod.set_workspace(None)
+    o1 = pirmod.answer(k1, Td)
+    torch.cuda.synchronize()
+    assert pirmod.check_status() == pirmod.PIR_OK
+    rec = pirmod.reconstruct(o0.cpu().numpy().view(np.uint32)[0], o1.cpu().numpy().view(np.uint32)[0])
+    assert (rec == W.table_rows_np(a, dim, 41)[0]).all()

@@ -75,3 +75,43 @@ def test_committed_cache_keeps_answers(O, pirmod):
             assert (got.cpu().numpy().view(np.uint32) == want).all(), (rows, dim, nkeys, prf)
     finally:
         pirmod.set_tuning([])
+
+
+@pytest.mark.parametrize("q", [1, 2])
+def test_tuned_small_groups_on_a_streamed_table(O, pirmod, q):
+    """Tuned plans of 1 or 2 keys per workgroup over 3 keys on a 1 GiB table
+    (2^22 x 64, AES-128, where one key alone takes the stream kernel): every
+    key is answered (both servers' calls reconstruct T[alpha] for all three),
+    and server 0's first and last keys match the oracle's point evaluation on
+    a sparse copy of the table."""
+    import torch
+
+    rows, dim, nkeys, seed = 1 << 22, 64, 3, 71
+    Td = W.make_table(rows, dim, seed, device="cuda")
+    a = W.uniform_indices(rows, nkeys, seed)
+    K0, K1 = O.gen_batch(22, a, W.key_seeds(nkeys, seed), prf_id=0)
+    pirmod.set_tuning([entry(pirmod, 0, 22, kernel=2, keys_per_item=q)])
+    try:
+        p = pirmod.plan(nkeys, rows, dim)
+        assert p["kernel"] == pirmod.KERNEL_SMALL_BATCH and p["keys_per_item"] == q, p
+        o0 = pirmod.answer(torch.from_numpy(K0).cuda(), Td)
+        o1 = pirmod.answer(torch.from_numpy(K1).cuda(), Td)
+        assert pirmod.check_status() == pirmod.PIR_OK
+        # the sparse copy: zero except 64 rows, so each key's answer is a sum of 64 point evaluations
+        rng = np.random.default_rng(seed)
+        keep = np.unique(np.concatenate([a, rng.integers(0, rows, 61)]))
+        vals = rng.integers(0, 1 << 32, (len(keep), dim), dtype=np.uint64).astype(np.uint32)
+        Sd = torch.zeros((rows, dim), dtype=torch.int32, device="cuda")
+        Sd[torch.from_numpy(keep).cuda()] = torch.from_numpy(vals.view(np.int32)).cuda()
+        s0 = pirmod.answer(torch.from_numpy(K0).cuda(), Sd)
+        torch.cuda.synchronize()
+    finally:
+        pirmod.set_tuning([])
+    rec = pirmod.reconstruct(o0.cpu().numpy().view(np.uint32).ravel(), o1.cpu().numpy().view(np.uint32).ravel())
+    assert (rec.reshape(nkeys, dim) == W.table_rows_np(a, dim, seed)).all()
+    got = s0.cpu().numpy().view(np.uint32)
+    for k in (0, nkeys - 1):
+        want = np.zeros(dim, np.uint64)
+        for r, v in zip(keep, vals):
+            want += np.uint64(O.eval_point(K0[k], int(r))) * v.astype(np.uint64)
+        assert (got[k] == (want & 0xFFFFFFFF).astype(np.uint32)).all(), k

@@ -100,9 +100,19 @@ def test_reconstruct_wraps():
 
 
 def test_strerror(lib):
-    for st in (0, -1, -2, -3, -4, 99):
+    for st in (0, -1, -2, -3, -4, -5, 99):
         assert isinstance(lib.pir_strerror(st), bytes)
-    assert lib.pir_strerror(pir.PIR_EKEY) != lib.pir_strerror(pir.PIR_OK)
+    msgs = {lib.pir_strerror(st) for st in (0, -1, -2, -3, -4, -5)}
+    assert len(msgs) == 6 and lib.pir_strerror(99) not in msgs
+    assert b"not valid" in lib.pir_strerror(pir.PIR_ESTALL)
+
+
+def test_wait_limit_is_set_and_restored_without_gpu(lib):
+    """The wait limit is host state (no HIP call): any value is accepted, 0
+    restores the default."""
+    for tries in (1, 7, 0, 2**32 - 1, 0):
+        assert lib.pir_set_wait_limit(tries) == pir.PIR_OK
+    pir.set_wait_limit(0)
 
 
 def test_answer_validation_without_gpu(lib):
@@ -261,6 +271,25 @@ def test_plan_single_key_spreads_over_every_cu():
     assert pir.plan(1, 1 << 22, 63)["kernel"] == pir.KERNEL_SMALL_BATCH
     assert pir.plan(1, 1 << 22, 16)["kernel"] == pir.KERNEL_SMALL_BATCH  # 256 MiB
     assert pir.plan(2, 1 << 25, 64)["kernel"] == pir.KERNEL_SMALL_BATCH
+
+
+def test_plan_tuned_one_key_per_group_over_several_keys_keeps_the_fused_kernel():
+    """The stream kernel answers one key: a tuned plan of one key per
+    workgroup over 3 keys on a table above 256 MiB stays on the small-batch
+    kernel (one group per key); a tuned group of 2 over a single key does not
+    stream either."""
+    T = pir.TUNE_MODEL
+    base = dict(prf_id=0, n=22, dim_lo=1, dim_hi=64, kernel=pir.KERNEL_SMALL_BATCH, subtree_log=0, tail_keys=T)
+    try:
+        pir.set_tuning([dict(base, keys_lo=3, keys_hi=3, keys_per_item=1),
+                        dict(base, keys_lo=1, keys_hi=1, keys_per_item=2)])
+        p = pir.plan(3, 1 << 22, 64)
+        assert p["kernel"] == pir.KERNEL_SMALL_BATCH and p["keys_per_item"] == 1 and p["items"] % 3 == 0, p
+        p = pir.plan(1, 1 << 22, 64)
+        assert p["kernel"] == pir.KERNEL_SMALL_BATCH and p["keys_per_item"] == 2, p
+    finally:
+        pir.set_tuning([])
+    assert pir.plan(1, 1 << 22, 64)["kernel"] == pir.KERNEL_STREAM
 
 
 def test_plan_small_wave_batches_fill_the_gpu():
