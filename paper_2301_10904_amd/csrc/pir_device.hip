@@ -46,17 +46,24 @@ static void launch_q(uint32_t kch, dim3 grid, hipStream_t st, const uint8_t *key
         // memory-side cache (256 MiB) its rows are read without allocating in
         // the caches (measured with AES-128: 2^22 x 64 0.235 -> 0.215 ms, 2^25
         // x 64 1.48 -> 1.44 ms; at 2^20 x 64, 256 MiB, cached reads are faster)
-        if (v4 && rows * dim * 4ull > (256ull << 20)) {
-            if (kch == 1 && PRF::TAB_WORDS && n_keys == 1 && g.H > SP_LGS && g.H <= SP_LGS + HMAX) {
-                // one key, rows of up to 64 words, AES-128: tree waves and table-stream
-                // waves (k_pir_stream; measured, 1 key: 2^25 x 64 1.476 ->
-                // 1.404 ms, 2^22 x 64 0.224 -> 0.206, 2^24 x 32 0.625 -> 0.587,
-                // 2^23 x 16 0.309 -> 0.281).  ChaCha20 keeps k_pir_fused, where
-                // the split gained nothing (2^25 x 64 1.541 against 1.568 ms)
-                hipLaunchKernelGGL((k_pir_stream<PRF>), grid, dim3(NT), 0, st, keys, table, rows, dim, out, g,
+        const bool big = rows * dim * 4ull > (256ull << 20);
+        if (v4 && kch == 1 && PRF::TAB_WORDS && n_keys == 1 && g.H > SP_LGS && g.H <= SP_LGS + HMAX) {
+            // one key, rows of up to 64 words, AES-128: tree waves and
+            // table-stream waves (k_pir_stream; measured, 1 key: 2^25 x 64
+            // 1.476 -> 1.404 ms, 2^22 x 64 0.224 -> 0.206, 2^24 x 32 0.625 ->
+            // 0.587, 2^23 x 16 0.309 -> 0.281; with cached row reads up to 256
+            // MiB: 2^20 x 64 0.080 -> 0.074, 2^19 x 64 0.060 -> 0.055, 2^14 x
+            // 16 0.036 -> 0.035).  ChaCha20 keeps k_pir_fused, where the split
+            // gained nothing (2^25 x 64 1.541 against 1.568 ms)
+            if (big)
+                hipLaunchKernelGGL((k_pir_stream<PRF, true>), grid, dim3(NT), 0, st, keys, table, rows, dim, out, g,
                                    status, g_wait_limit.load(std::memory_order_relaxed));
-                return;
-            }
+            else
+                hipLaunchKernelGGL((k_pir_stream<PRF, false>), grid, dim3(NT), 0, st, keys, table, rows, dim, out, g,
+                                   status, g_wait_limit.load(std::memory_order_relaxed));
+            return;
+        }
+        if (v4 && big) {
             if (kch == 1)
                 PIR_LAUNCH_FUSED(1, true, true);
             else if (kch == 2)
@@ -748,8 +755,8 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
     out->items = p.grid;
     out->workgroups = p.grid;
     out->lanes_per_workgroup = NT;
-    if (aes && p.Q == 1 && n_keys == 1 && p.kch == 1 && dim % 4 == 0 && rows * dim * 4ull > (256ull << 20) &&
-        p.g.H > SP_LGS && p.g.H <= SP_LGS + HMAX) { // (for a 16-byte aligned table)
+    if (aes && p.Q == 1 && n_keys == 1 && p.kch == 1 && dim % 4 == 0 && p.g.H > SP_LGS &&
+        p.g.H <= SP_LGS + HMAX) { // (for a 16-byte aligned table)
         out->kernel = PIR_KERNEL_STREAM;
         out->lds_bytes = (uint32_t)sizeof(Smem<AesPrf::TAB_WORDS>) + 64 * PIR_MAX_LOG_DOMAIN;
         out->keys_per_item = 1;

@@ -755,8 +755,10 @@ __global__ __launch_bounds__(NT) void k_pir_fused(const uint8_t *__restrict__ ke
 }
 
 // ---------------------------------------------------------------------------
-// One key on a large table (above the memory-side cache): the table stream,
-// not the tree, bounds the call, so the waves of a workgroup split the work.
+// One key: the table stream, not the tree, bounds the call on large tables,
+// and on small ones the rows wait on the tree's dependent chain; so the waves
+// of a workgroup split the work.  STREAM: rows read without allocating in the
+// caches (a table above the memory-side cache, read once).
 // Waves 0 .. SP_WAVES-1 (producers) walk the key's subtrees, one lane per
 // subtree as in k_pir_fused, and write each step's leaf shares into an LDS ring
 // of SP_RING steps; the other waves (consumers) stream the table rows of each
@@ -792,7 +794,7 @@ __device__ __forceinline__ bool wait_count(uint32_t *ctr, uint32_t target, uint3
     return false;
 }
 
-template <class PRF>
+template <class PRF, bool STREAM>
 __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_stream(const uint8_t *__restrict__ keys,
                                                    const uint32_t *__restrict__ table, uint64_t rows, uint32_t dim,
                                                    uint32_t *__restrict__ out, Geometry g, uint32_t *status,
@@ -894,7 +896,7 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
                     const uint32_t k = c * SP_ROWS_PER_WAVE + r0 + 4 * u + rs;
                     const uint64_t row = row_base + ((uint64_t)(k >> 1) << h) + 2 * m + (k & 1);
                     const uint32_t *trow = table + (row < rows ? row : rows - 1) * dim;
-                    tv[u] = col_ok ? row_load4<true>(trow + col) : make_uint4(0, 0, 0, 0);
+                    tv[u] = col_ok ? row_load4<STREAM>(trow + col) : make_uint4(0, 0, 0, 0);
                 }
             };
             load_round(0);

@@ -252,24 +252,27 @@ def test_plan_batched_default_workload():
 
 def test_plan_single_key_spreads_over_every_cu():
     """One key: about two workgroups per CU of the 256, each covering its own
-    rows; the small-batch kernel up to 256 MiB of table, above it with
-    AES-128 the stream kernel (256 tree lanes per workgroup: 8 breadth-first
-    levels) while its subtree height fits the path registers."""
+    rows; with AES-128 the stream kernel (256 tree lanes per workgroup: 8
+    breadth-first levels) while its subtree height fits the path registers,
+    otherwise, and with ChaCha20, the small-batch kernel."""
     for rows in (1 << 20, 1 << 22, 1 << 25, 1 << 32):
         for prf in ("aes128", "chacha20"):
             p = pir.plan(1, rows, 64, prf=prf)
-            stream = prf == "aes128" and 1 << 20 < rows < 1 << 32
+            stream = prf == "aes128" and rows < 1 << 32
             assert p["kernel"] == (pir.KERNEL_STREAM if stream else pir.KERNEL_SMALL_BATCH), (rows, prf, p)
             assert p["bfs_levels"] == (8 if stream else 9)
             assert p["workgroups"] >= 2 * 256, (rows, p)
             assert p["workgroups"] * p["rows_per_item"] >= rows
             assert p["descent_levels"] + p["bfs_levels"] + p["subtree_log"] == p["n"]
-    # rows of 16, 32 or 64 words stream; wider rows and tables up to 256 MiB do not
-    assert pir.plan(1, 1 << 23, 16)["kernel"] == pir.KERNEL_STREAM
-    assert pir.plan(1, 1 << 22, 32)["kernel"] == pir.KERNEL_STREAM
-    assert pir.plan(1, 1 << 22, 100)["kernel"] == pir.KERNEL_SMALL_BATCH
-    assert pir.plan(1, 1 << 22, 63)["kernel"] == pir.KERNEL_SMALL_BATCH
-    assert pir.plan(1, 1 << 22, 16)["kernel"] == pir.KERNEL_SMALL_BATCH  # 256 MiB
+    # rows of 16, 32 or 64 words stream, on small tables too (cached row reads
+    # up to 256 MiB); wider rows, rows of a width not a multiple of 4 words,
+    # tables of at most 256 rows (no subtree below 256 tree lanes), and two
+    # keys do not
+    for rows, dim in ((1 << 23, 16), (1 << 22, 32), (1 << 22, 16), (1 << 14, 16), (1 << 10, 64), (257, 4)):
+        p = pir.plan(1, rows, dim)
+        assert p["kernel"] == pir.KERNEL_STREAM and p["subtree_log"] >= 1, (rows, dim, p)
+    for rows, dim in ((1 << 22, 100), (1 << 22, 63), (1 << 8, 64), (100, 16)):
+        assert pir.plan(1, rows, dim)["kernel"] == pir.KERNEL_SMALL_BATCH, (rows, dim)
     assert pir.plan(2, 1 << 25, 64)["kernel"] == pir.KERNEL_SMALL_BATCH
 
 
