@@ -252,6 +252,10 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=64,
                     help="keys of the workload the oracle answers for the CPU baseline (x8 for ChaCha20)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-configs", dest="configs", action="store_false",
+                    help="skip the records of the other workloads in the default line (1: 2^14 x 16 one pair "
+                         "per call; 3: 8 tables, ragged Zipf batches; 5: serving; the ChaCha20 PRF on the "
+                         "default workload)")
     ap.add_argument("--large-keys", type=int, default=2048, metavar="PAIRS",
                     help="key pairs per launch of the 2^25 x 64 record in the default line (0: omit it)")
     ap.add_argument("--large-steps", type=int, default=3,
@@ -423,6 +427,8 @@ def main():
 
     # config 4 beside the default line: the 8 GiB table, its largest batch
     large = large_batch_record(prf, args.large_keys, args.large_steps) if args.large_keys else None
+    # configs 1, 3 and 5 and the other PRF, each a record of its own
+    others = other_configs(prf) if args.configs else None
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -465,6 +471,7 @@ def main():
         "measured_peaks": peaks,
         "cpu_baseline": cpu,
         "large_table": large,
+        "other_configs": others,
         "plan": {"kernel": kernel, "source": "tuned" if plan["source"] == pir.PLAN_TUNED else "model",
                  "subtree_log": plan["subtree_log"], "keys_per_item": plan["keys_per_item"],
                  "tuning": args.tuning},
@@ -709,6 +716,106 @@ def prf_sweep(args):
                                    "counter blocks 0 and 1), no codewords, table or contraction"}}
 
 
+def small_record(prf: str, steps: int, warmup: int) -> dict:
+    """Config 1: one table of 2^14 rows x 16 uint32, one key pair (both
+    servers' keys) per call; every reconstruction checked."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    rows, dim = 1 << 14, 16
+    T = W.make_table(rows, dim, 1, device=dev)
+    a = W.uniform_indices(rows, 1, 1)
+    K0, K1 = pir.gen_batch(14, a, W.key_seeds(1, 1), prf=prf)
+    keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
+    out = torch.empty((2, dim), dtype=torch.int32, device=dev)
+    sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=prf), steps, warmup)
+    got = out.cpu().numpy().view(np.uint32)
+    ok = bool((pir.reconstruct(got[0], got[1]) == W.table_rows_np(a, dim, 1)[0]).all())
+    return {"value": round(2 / sec, 1), "exact": ok, "p50_ms": round(percentile(ms, 50), 4),
+            "p99_ms": round(percentile(ms, 99), 4), "calls": steps,
+            "config": {"workload": "one table 2^14 x 16 uint32, one key pair per call"}}
+
+
+def multi_record(prf: str, steps: int, warmup: int) -> dict:
+    """Config 3: 8 tables of 2^16..2^23 rows x 32 uint32 (2 GiB), ragged
+    Zipf(1.05) batches of 32..1024 queries (both servers' keys), one call;
+    every reconstruction checked."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    seed = 3
+    dev = torch.device("cuda:0")
+    sizes = W.ragged_batch_sizes(8, seed)
+    tables, counts, keys_l, alphas = [], [], [], []
+    for t in range(8):
+        rows = 1 << (16 + t)
+        tables.append(W.make_table(rows, 32, seed + t, device=dev))
+        a = W.zipf_indices(rows, int(sizes[t]), seed + t)
+        K0, K1 = pir.gen_batch(16 + t, a, W.key_seeds(len(a), seed + t), prf=prf)
+        keys_l.append(np.concatenate([K0, K1]))
+        counts.append(2 * int(sizes[t]))
+        alphas.append(a)
+    stride = (max(k.shape[1] for k in keys_l) + 15) // 16 * 16
+    keys = torch.from_numpy(np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keys_l])).to(dev)
+    out, views = pir.answer_multi(tables, counts, keys, prf=prf)
+    sec, ms = time_launches(lambda: pir.answer_multi(tables, counts, keys, out=out, prf=prf), steps, warmup)
+    ok = True
+    for t in range(8):
+        got = views[t].cpu().numpy().view(np.uint32)
+        B = counts[t] // 2
+        rec = ((got[:B].astype(np.uint64) + got[B:]) & 0xFFFFFFFF).astype(np.uint32)
+        ok &= bool((rec == W.table_rows_np(alphas[t], 32, seed + t)).all())
+    return {"value": round(sum(counts) / sec, 1), "exact": ok, "ms_per_call": round(sec * 1e3, 3), "calls": steps,
+            "config": {"workload": "8 tables 2^16..2^23 rows x 32 uint32 (2 GiB), ragged batches of "
+                                   "32..1024 queries (both servers' keys), Zipf(1.05), one call",
+                       "queries_per_table": [int(x) for x in sizes], "keys_per_call": sum(counts)}}
+
+
+def prf_record(prf: str, steps: int) -> dict:
+    """The default workload (2^20 x 64, 1024 keys per launch) with another
+    PRF: one warm-up and `steps` timed launches, every reconstruction checked,
+    and the kernel's roofline."""
+    import torch
+
+    from paper_2301_10904_amd import pir
+    from paper_2301_10904_amd import workloads as W
+
+    dev = torch.device("cuda:0")
+    rows, dim, pairs, seed = 1 << 20, 64, 512, 1
+    T = W.make_table(rows, dim, seed, device=dev)
+    a = W.uniform_indices(rows, pairs, seed)
+    K0, K1 = pir.gen_batch(20, a, W.key_seeds(pairs, seed), prf=prf)
+    keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
+    out = torch.empty((2 * pairs, dim), dtype=torch.int32, device=dev)
+    sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=prf), steps, 1)
+    got = out.cpu().numpy().view(np.uint32)
+    rec = ((got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF).astype(np.uint32)
+    ok = bool((rec == W.table_rows_np(a, dim, seed)).all())
+    kern = KERNEL_NAMES[pir.plan(2 * pairs, rows, dim, prf=prf)["kernel"]]
+    roofline = rooflines(prf, 20, 2 * pairs, dim, float(np.mean(ms)) / 1e3, kern)[0]
+    return {"prf": prf, "server_qps": round(2 * pairs / sec, 1), "ms_per_launch": [round(x, 3) for x in ms],
+            "exact": ok, "kernel": kern, "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac")},
+            "workload": f"one table 2^20 rows x 64 uint32, {2 * pairs} keys per launch, uniform alpha, {prf}"}
+
+
+def other_configs(prf: str) -> dict:
+    """Records of the other workloads beside the default line: config 1,
+    config 3, one point of each serving mix (config 5), and the default
+    workload with the other PRF."""
+    other = "chacha20" if prf == "aes128" else "aes128"
+    serve = serve_sweep(argparse.Namespace(prf=prf), points=(("uniform", 50000), ("inv_rows", 50000)), dur=1.0)
+    return {"config1_small": small_record(prf, 200, 10),
+            "config3_multi": multi_record(prf, 3, 1),
+            "config5_serve": {k: serve[k] for k in ("exact", "serve", "config")},
+            f"{other}_default_workload": prf_record(other, 3)}
+
+
+
 def time_launches(fn, steps, warmup):
     """Average seconds per call of fn() (event-bracketed on the current stream) and per-call ms."""
     import torch
@@ -754,44 +861,9 @@ def other_modes(args):
     line = {"metric": METRIC, "unit": "server queries/s", "n_gpus": 1, "higher_is_better": True,
             "dtype": "u32", "data": "synthetic", "mode": args.mode, "prf": prf, "plans": args.tuning}
     if args.mode == "small":
-        rows, dim = 1 << 14, 16
-        T = W.make_table(rows, dim, 1, device=dev)
-        a = W.uniform_indices(rows, 1, 1)
-        K0, K1 = pir.gen_batch(14, a, W.key_seeds(1, 1), prf=prf)
-        keys = torch.from_numpy(np.concatenate([K0, K1])).to(dev)
-        out = torch.empty((2, dim), dtype=torch.int32, device=dev)
-        sec, ms = time_launches(lambda: pir.answer(keys, T, out, prf=prf), 200, 10)
-        got = out.cpu().numpy().view(np.uint32)
-        ok = bool((pir.reconstruct(got[0], got[1]) == W.table_rows_np(a, dim, 1)[0]).all())
-        line.update(value=round(2 / sec, 1), exact=ok, p50_ms=round(percentile(ms, 50), 4),
-                    p99_ms=round(percentile(ms, 99), 4),
-                    config={"workload": "one table 2^14 x 16 uint32, one key pair per call"})
+        line.update(small_record(prf, 200, 10))
     elif args.mode == "multi":
-        seed = 3
-        sizes = W.ragged_batch_sizes(8, seed)
-        tables, counts, keys_l, alphas = [], [], [], []
-        for t in range(8):
-            rows = 1 << (16 + t)
-            tables.append(W.make_table(rows, 32, seed + t, device=dev))
-            a = W.zipf_indices(rows, int(sizes[t]), seed + t)
-            K0, K1 = pir.gen_batch(16 + t, a, W.key_seeds(len(a), seed + t), prf=prf)
-            keys_l.append(np.concatenate([K0, K1]))
-            counts.append(2 * int(sizes[t]))
-            alphas.append(a)
-        stride = (max(k.shape[1] for k in keys_l) + 15) // 16 * 16
-        keys = torch.from_numpy(np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keys_l])).to(dev)
-        out, views = pir.answer_multi(tables, counts, keys, prf=prf)
-        sec, ms = time_launches(lambda: pir.answer_multi(tables, counts, keys, out=out, prf=prf), 5, 1)
-        ok = True
-        for t in range(8):
-            got = views[t].cpu().numpy().view(np.uint32)
-            B = counts[t] // 2
-            rec = ((got[:B].astype(np.uint64) + got[B:]) & 0xFFFFFFFF).astype(np.uint32)
-            ok &= bool((rec == W.table_rows_np(alphas[t], 32, seed + t)).all())
-        line.update(value=round(sum(counts) / sec, 1), exact=ok, ms_per_call=round(sec * 1e3, 3),
-                    config={"workload": "8 tables 2^16..2^23 rows x 32 uint32 (2 GiB), ragged batches of "
-                                        "32..1024 queries (both servers' keys), Zipf(1.05), one call",
-                            "queries_per_table": [int(x) for x in sizes], "keys_per_call": sum(counts)})
+        line.update(multi_record(prf, 5, 1))
     elif args.mode == "large":
         rows, dim, seed = 1 << 25, 64, 4
         T = W.make_table(rows, dim, seed, device=dev)
@@ -1120,8 +1192,12 @@ def hotfull_run(args):
                                    f"{clients} clients per server, both servers in one call", "prf": args.prf}}
 
 
-def serve_sweep(args):
-    """Poisson arrivals over 4 resident tables (2^18, 2^20, 2^22, 2^24 rows x 32 uint32)."""
+SERVE_POINTS = tuple((mix, rate) for mix in ("uniform", "inv_rows") for rate in (20000, 50000, 100000, 200000))
+
+
+def serve_sweep(args, points=SERVE_POINTS, dur: float = 1.5):
+    """Poisson arrivals over 4 resident tables (2^18, 2^20, 2^22, 2^24 rows x
+    32 uint32), at each (mix, offered requests/s) of `points` for `dur` s."""
     import torch
 
     from paper_2301_10904_amd import pir
@@ -1154,24 +1230,22 @@ def serve_sweep(args):
             bad.append((t, int(ki), int(np.sum(pir.reconstruct(row, other) != want))))
 
     runs = []
-    dur = 1.5
-    for mix in ("uniform", "inv_rows"):
+    for mix, rate in points:
         w = np.ones(4) if mix == "uniform" else np.array([1.0 / (1 << lg) for lg in logs])
         w = w / w.sum()
-        for rate in (20000, 50000, 100000, 200000):
-            n = int(rate * dur)
-            arr = W.poisson_arrivals(rate, n, 7)
-            rng = np.random.default_rng([rate, len(mix)])
-            tids = rng.choice(4, n, p=w)
-            kidx = rng.integers(0, 1024, n)
-            stats = srv.run(arr, tids, pool, kidx, stride, check=check)
-            r = stats.summary()
-            r.update(mix=mix, offered_qps=rate)
-            runs.append(r)
+        n = int(rate * dur)
+        arr = W.poisson_arrivals(rate, n, 7)
+        rng = np.random.default_rng([rate, len(mix)])
+        tids = rng.choice(4, n, p=w)
+        kidx = rng.integers(0, 1024, n)
+        stats = srv.run(arr, tids, pool, kidx, stride, check=check)
+        r = stats.summary()
+        r.update(mix=mix, offered_qps=rate)
+        runs.append(r)
     return {"value": max(r["sustained_qps"] for r in runs), "exact": not bad, "check_failures": bad[:8],
             "serve": runs,
             "config": {"workload": "4 resident tables 2^18, 2^20, 2^22, 2^24 rows x 32 uint32 (2.7 GiB), "
-                                   "Poisson arrivals 20k..200k requests/s, one key per request, "
+                                   f"Poisson arrivals at {sorted({r for _, r in points})} requests/s, one key per request, "
                                    "batched by table (up to 2^29 leaves per table per batch, 3 batches in flight), "
                                    "admitted while the queued work drains within 0.1 s at the measured service rate",
                        "duration_s": dur}}
