@@ -47,21 +47,25 @@ static void launch_q(uint32_t kch, dim3 grid, hipStream_t st, const uint8_t *key
         // the caches (measured with AES-128: 2^22 x 64 0.235 -> 0.215 ms, 2^25
         // x 64 1.48 -> 1.44 ms; at 2^20 x 64, 256 MiB, cached reads are faster)
         const bool big = rows * dim * 4ull > (256ull << 20);
-        if (v4 && kch == 1 && PRF::TAB_WORDS && n_keys == 1 && g.H > SP_LGS && g.H <= SP_LGS + HMAX) {
-            // one key, rows of up to 64 words, AES-128: tree waves and
-            // table-stream waves (k_pir_stream; measured, 1 key: 2^25 x 64
-            // 1.476 -> 1.404 ms, 2^22 x 64 0.224 -> 0.206, 2^24 x 32 0.625 ->
-            // 0.587, 2^23 x 16 0.309 -> 0.281; with cached row reads up to 256
-            // MiB: 2^20 x 64 0.080 -> 0.074, 2^19 x 64 0.060 -> 0.055, 2^14 x
-            // 16 0.036 -> 0.035).  ChaCha20 keeps k_pir_fused, where the split
-            // gained nothing (2^25 x 64 1.541 against 1.568 ms)
-            if (big)
-                hipLaunchKernelGGL((k_pir_stream<PRF, true>), grid, dim3(NT), 0, st, keys, table, rows, dim, out, g,
-                                   status, g_wait_limit.load(std::memory_order_relaxed));
-            else
-                hipLaunchKernelGGL((k_pir_stream<PRF, false>), grid, dim3(NT), 0, st, keys, table, rows, dim, out, g,
-                                   status, g_wait_limit.load(std::memory_order_relaxed));
-            return;
+        if constexpr (PRF::TAB_WORDS != 0) {
+            if (v4 && kch == 1 && n_keys == 1 && g.H > SP_LGS && g.H <= SP_LGS + HMAX) {
+                // one key, rows of up to 64 words, AES-128: tree waves and
+                // table-stream waves (k_pir_stream; measured, 1 key: 2^25 x
+                // 64 1.476 -> 1.404 ms, 2^22 x 64 0.224 -> 0.206, 2^24 x 32
+                // 0.625 -> 0.587, 2^23 x 16 0.309 -> 0.281; with cached row
+                // reads up to 256 MiB: 2^20 x 64 0.080 -> 0.074, 2^19 x 64
+                // 0.060 -> 0.055, 2^14 x 16 0.036 -> 0.035).  ChaCha20 keeps
+                // k_pir_fused, where the split gained at most 3% and lost at
+                // some sizes (2^25 x 64 1.541 against 1.568 ms, 2^20 x 64
+                // 0.068 against 0.066)
+                if (big)
+                    hipLaunchKernelGGL((k_pir_stream<PRF, true>), grid, dim3(NT), 0, st, keys, table, rows, dim, out,
+                                       g, status, g_wait_limit.load(std::memory_order_relaxed));
+                else
+                    hipLaunchKernelGGL((k_pir_stream<PRF, false>), grid, dim3(NT), 0, st, keys, table, rows, dim, out,
+                                       g, status, g_wait_limit.load(std::memory_order_relaxed));
+                return;
+            }
         }
         if (v4 && big) {
             if (kch == 1)
