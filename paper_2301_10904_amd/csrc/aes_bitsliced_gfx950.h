@@ -255,7 +255,6 @@ constexpr P256 inv(P256 a)
     return {mul(a.h, di), mul(add(a.h, a.l), di)};
 }
 
-// S-box in place on the planes x[0..7] (x[k] = bit k of the byte).
 // XOR of v[j] over the set bits j of `mask` (at most 8), onto `init`, three
 // inputs per operation
 constexpr uint32_t xor_select(uint32_t init, uint32_t mask, const uint32_t *v)
@@ -284,6 +283,9 @@ constexpr uint32_t matrix_row(const uint8_t *col, int j)
     return r;
 }
 
+// S-box in place on the planes x[0..7] (x[k] = bit k of the byte): the input
+// change of basis, the tower-field inverse, then the output change of basis
+// merged with the affine map and its constant {63}.
 constexpr void sbox_planes(uint32_t *x)
 {
     uint32_t t[8] = {};
