@@ -988,7 +988,7 @@ def batch_sweep(args):
             autotune.system_identity()["arch"]).read_text()))
 
     def describe(plan, B):
-        kern = "waves" if plan["kernel"] == pir.KERNEL_WAVES else "small_batch"
+        kern = {pir.KERNEL_WAVES: "waves", pir.KERNEL_STREAM: "stream"}.get(plan["kernel"], "small_batch")
         if plan["tail_keys"]:
             kern += f" ({B - plan['tail_keys']} keys) + remainder ({plan['tail_keys']} keys)"
         return kern
