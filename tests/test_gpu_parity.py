@@ -792,6 +792,27 @@ def test_table_at_a_4_byte_offset(O, pirmod, prf, rows, dim, nkeys):
         assert (v.cpu().numpy().view(np.uint32) == want).all()
 
 
+@pytest.mark.parametrize("rows,dim", [(257, 4), (1000, 16), (3000, 64), (5000, 32), (1 << 16, 64), (100000, 16)])
+def test_single_key_stream_kernel_small_tables(O, pirmod, rows, dim):
+    """One AES-128 key on tables of 257 to 100,000 rows (most of them ragged)
+    takes k_pir_stream with cached row reads; both parties' answers against
+    the full oracle and the reconstruction of the last row and of a random one."""
+    assert pirmod.plan(1, rows, dim)["kernel"] == pirmod.KERNEL_STREAM
+    seed = rows + dim
+    n = log_domain(rows)
+    T = W.make_table(rows, dim, seed)
+    Tn, Td = T.numpy().view(np.uint32), T.cuda()
+    alphas = [rows - 1, int(W.uniform_indices(rows, 1, seed)[0])]
+    K0, K1 = O.gen_batch(n, np.array(alphas, dtype=np.int64), W.key_seeds(2, seed), prf_id=0)
+    for i, a in enumerate(alphas):
+        g0 = gpu_answer(pirmod, K0[i:i + 1], Td)
+        g1 = gpu_answer(pirmod, K1[i:i + 1], Td)
+        assert (g0 == O.answer_batch(K0[i:i + 1], Tn, nthreads=cpu_threads())).all(), (rows, dim, a)
+        assert (g1 == O.answer_batch(K1[i:i + 1], Tn, nthreads=cpu_threads())).all(), (rows, dim, a)
+        assert (O.reconstruct(g0[0], g1[0]) == Tn[a]).all()
+    assert pirmod.check_status() == pirmod.PIR_OK
+
+
 @pytest.mark.parametrize("prf", [0, 1])
 @pytest.mark.parametrize("rows,dim", [(1 << 21, 64), ((1 << 22) + 12345, 40), (1 << 23, 16)])
 def test_single_key_stream_kernel_dense(O, pirmod, prf, rows, dim):
