@@ -407,7 +407,7 @@ def main():
 
     kern_s = float(np.mean(launch_ms)) / 1e3
     plan = pir.plan(B, rows, dim, prf=prf)
-    kernel = KERNEL_NAMES[plan["kernel"]]
+    kernel = kernel_name(plan, dim)
     roofline, roofline_lds, roofline_valu = rooflines(prf, n, B, dim, kern_s, kernel)
     # the fused kernel's tree nodes per second against the PRF engine alone
     # (the same node mix, tables and workgroups, nothing else), and the
@@ -484,6 +484,12 @@ def main():
 KERNEL_NAMES = {1: "k_pir_waves", 2: "k_pir_fused", 3: "k_pir_stream"}
 
 
+def kernel_name(plan: dict, dim: int) -> str:
+    """The kernel a plan launches (rows of 65-128 words run the wave kernel as wave pairs)."""
+    name = KERNEL_NAMES[plan["kernel"]]
+    return name + "_pairs" if name == "k_pir_waves" and dim > 64 else name
+
+
 def rooflines(prf: str, n: int, keys: int, dim: int, kern_s: float, kernel: str):
     """(roofline, roofline_lds, roofline_valu) of a launch of `keys` keys over
     2^n rows that took kern_s seconds.  The binding unit: LDS table lookups
@@ -542,7 +548,7 @@ def large_batch_record(prf: str, pairs: int, steps: int) -> dict:
                        f"per launch, uniform alpha, {'AES-128' if prf == 'aes128' else 'ChaCha20'} PRF",
            "keys_per_launch": B, "warmup": 1, "steps": steps, "server_qps": round(B / sec, 1),
            "ms_per_launch": [round(x, 2) for x in ms], "exact": exact,
-           "kernel": KERNEL_NAMES[pir.plan(B, rows, dim, prf=prf)["kernel"]],
+           "kernel": kernel_name(pir.plan(B, rows, dim, prf=prf), dim),
            "single_query": {"p50_ms": round(p50, 4), "p99_ms": round(percentile(ms1, 99), 4), "samples": len(ms1),
                             "roofline": {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS,
                                          "unit": "GB/s", "frac": round(gbs / HBM_PEAK_GBS, 4)}}}
@@ -796,7 +802,7 @@ def prf_record(prf: str, steps: int) -> dict:
     got = out.cpu().numpy().view(np.uint32)
     rec = ((got[:pairs].astype(np.uint64) + got[pairs:]) & 0xFFFFFFFF).astype(np.uint32)
     ok = bool((rec == W.table_rows_np(a, dim, seed)).all())
-    kern = KERNEL_NAMES[pir.plan(2 * pairs, rows, dim, prf=prf)["kernel"]]
+    kern = kernel_name(pir.plan(2 * pairs, rows, dim, prf=prf), dim)
     roofline = rooflines(prf, 20, 2 * pairs, dim, float(np.mean(ms)) / 1e3, kern)[0]
     return {"prf": prf, "server_qps": round(2 * pairs / sec, 1), "ms_per_launch": [round(x, 3) for x in ms],
             "exact": ok, "kernel": kern, "roofline": {k: roofline[k] for k in ("bound", "achieved", "peak", "unit", "frac")},

@@ -215,7 +215,10 @@ int pir_answer_bins(uint32_t prf_id, const pir_bins_t *tables, uint32_t n_tables
  * batch scheduling of sections 3.2.1 and 3.2.5), for inspection and tests; it
  * launches nothing and needs no GPU.  PIR_EINVAL for an unknown prf_id, no
  * keys, or sizes pir_answer rejects; PIR_ENOMEM where pir_answer would. */
-#define PIR_KERNEL_WAVES 1       /* batched: up to 16 keys per wave, int8 matrix cores */
+#define PIR_KERNEL_WAVES 1       /* batched: up to 16 keys per wave, int8 matrix cores; rows of
+                                    65-128 words run as wave pairs (two waves on the same keys
+                                    and adjacent chunks trade leaf shares, each multiplies one
+                                    64-column half), items counted per wave, in pairs */
 #define PIR_KERNEL_SMALL_BATCH 2 /* small batches (or rows > 128 words): 512-lane workgroups */
 #define PIR_KERNEL_STREAM 3      /* one AES-128 key on a table above 256 MiB with rows of at
                                     most 64 words (a multiple of 4, 16-byte aligned): tree

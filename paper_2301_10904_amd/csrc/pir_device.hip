@@ -207,7 +207,7 @@ static uint32_t wave_hmax(uint32_t m) { return m >= 3 ? std::min<uint32_t>(HMAX3
 // wave_hmax(m) for the aligned subtree of height m holding a bin (or a table
 // slice); a single table gets the height of wave_height(), a launch of several
 // tables the largest (the tables together fill the GPU).
-static uint64_t plan_waves(WaveTask *ts, uint32_t count, uint32_t h_want = 0)
+static uint64_t plan_waves(WaveTask *ts, uint32_t count, uint32_t h_want = 0, bool pairs = false)
 {
     uint64_t items = 0;
     for (uint32_t i = 0; i < count; i++) {
@@ -226,7 +226,9 @@ static uint64_t plan_waves(WaveTask *ts, uint32_t count, uint32_t h_want = 0)
         t.h = h;
         t.chunks_per_bin = (uint32_t)chunks_per_bin(h);
         t.item_begin = (uint32_t)items;
-        items += (uint64_t)t.n_bins * t.chunks_per_bin * t.n_groups;
+        // wave pairs (rows of 65-128 words) take a bin's chunks two at a time
+        const uint64_t per_bin = pairs ? 2 * (((uint64_t)t.chunks_per_bin + 1) / 2) : t.chunks_per_bin;
+        items += (uint64_t)t.n_bins * per_bin * t.n_groups;
         if (items >= ((uint64_t)1 << 31))
             return 0;
     }
@@ -235,7 +237,9 @@ static uint64_t plan_waves(WaveTask *ts, uint32_t count, uint32_t h_want = 0)
 
 // Column class of the wave kernel, which picks its instantiation (KT, VEC):
 // tables in one launch must share it.  The vector-load classes 0..2 need a
-// 16-byte aligned table; others of those widths read single words.
+// 16-byte aligned table; others of those widths read single words.  Rows of
+// 65-128 words run as wave pairs (k_pir_waves_pairs), with 16-byte loads
+// (class 7) when the width is a multiple of 4 and the table is aligned.
 static int wave_class(uint32_t dim, bool aligned)
 {
     if (dim == 64 && aligned) return 0;
@@ -244,10 +248,19 @@ static int wave_class(uint32_t dim, bool aligned)
     if (dim <= 16) return 3;
     if (dim <= 32) return 4;
     if (dim <= 64) return 5;
+    if (dim > 64 && dim <= 128 && dim % 4 == 0 && aligned) return 7;
     if (dim <= 128) return 6;
     return -1;
 }
-constexpr int WAVE_CLASSES = 7;
+constexpr int WAVE_CLASSES = 8;
+static bool wave_pairs(uint32_t dim) { return dim > 64; }
+// Static LDS of a wave-kernel workgroup for rows of dim words.
+static uint32_t wave_lds_bytes(bool aes, uint32_t dim)
+{
+    if (wave_pairs(dim))
+        return aes ? (uint32_t)sizeof(PairSmem<AesPrf::TAB_WORDS>) : (uint32_t)sizeof(PairSmem<1>);
+    return aes ? AES_TAB_WORDS * 4 : 0;
+}
 
 // Wave-kernel launch for up to MAX_TASKS tables of column class cls.  Plans
 // the tasks and clears their outputs first.
@@ -259,7 +272,7 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, int c
     bool any = false;
     for (uint32_t i = 0; i < count; i++)
         any |= ts[i].n_keys > 0;
-    const uint64_t items = plan_waves(ts, count, h_want);
+    const uint64_t items = plan_waves(ts, count, h_want, cls >= 6);
     if (items == 0 && any)
         return PIR_ENOMEM;
     if (!ctx.word())
@@ -285,9 +298,14 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, int c
     case 3: PIR_LAUNCH_WAVES(1, false); break;
     case 4: PIR_LAUNCH_WAVES(2, false); break;
     case 5: PIR_LAUNCH_WAVES(4, false); break;
-    case 6: PIR_LAUNCH_WAVES(8, false); break;
+#define PIR_LAUNCH_PAIRS(VEC)                                                                                      \
+    hipLaunchKernelGGL((k_pir_waves_pairs<PRF, VEC>), grid, dim3(NT3), 0, st, W, key_stride,                        \
+                       g_wait_limit.load(std::memory_order_relaxed))
+    case 6: PIR_LAUNCH_PAIRS(false); break;
+    case 7: PIR_LAUNCH_PAIRS(true); break;
     default: return PIR_EINVAL;
     }
+#undef PIR_LAUNCH_PAIRS
 #undef PIR_LAUNCH_WAVES
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? PIR_OK : fail_hip(e);
@@ -737,14 +755,14 @@ int pir_plan(uint32_t prf_id, uint32_t n_keys, uint64_t rows, uint32_t dim, pir_
         t.n_keys = n_keys;
         t.n = n;
         t.n_bins = 1;
-        const uint64_t items = plan_waves(&t, 1, c.h);
+        const uint64_t items = plan_waves(&t, 1, c.h, wave_pairs(dim));
         if (items == 0)
             return PIR_ENOMEM;
         out->kernel = PIR_KERNEL_WAVES;
         out->items = items;
         out->workgroups = (items + NW3 - 1) / NW3;
         out->lanes_per_workgroup = NT3;
-        out->lds_bytes = aes ? AES_TAB_WORDS * 4 : 0;
+        out->lds_bytes = wave_lds_bytes(aes, dim);
         out->keys_per_item = 16;
         out->rows_per_item = (uint64_t)4 << t.h;
         out->subtree_log = t.h;
@@ -821,7 +839,7 @@ int pir_plan_bins(uint32_t prf_id, uint64_t rows, uint32_t dim, uint32_t n_clien
     t.n_keys = n_clients;
     t.n = bin_log;
     t.n_bins = (uint32_t)((rows + ((uint64_t)1 << bin_log) - 1) >> bin_log);
-    const uint64_t items = plan_waves(&t, 1);
+    const uint64_t items = plan_waves(&t, 1, 0, wave_pairs(dim));
     if (items == 0)
         return PIR_ENOMEM;
     *out = pir_plan_t{};
@@ -830,7 +848,7 @@ int pir_plan_bins(uint32_t prf_id, uint64_t rows, uint32_t dim, uint32_t n_clien
     out->items = items;
     out->workgroups = (items + NW3 - 1) / NW3;
     out->lanes_per_workgroup = NT3;
-    out->lds_bytes = prf_id == PIR_PRF_AES128 ? AES_TAB_WORDS * 4 : 0;
+    out->lds_bytes = wave_lds_bytes(prf_id == PIR_PRF_AES128, dim);
     out->keys_per_item = 16;
     out->subtree_log = t.h;
     out->rows_per_item = (uint64_t)4 << t.h;

@@ -961,10 +961,11 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // hold an [16 keys x 8 rows] share tile, exactly the A operand layout of
 // v_mfma_i32_16x16x32_i8 (lane l: row l mod 16, K slice (l / 16) * 8 .. +7),
 // and mfma_step() multiplies it into the table rows: KT output tiles of 16
-// columns, for rows of up to 16 KT words (KT <= 8).  At KT = 8 a lane needs
-// more than 128 VGPRs, so one workgroup fits a CU instead of two.
+// columns, for rows of up to 16 KT words (KT <= 4, two workgroups per CU at
+// 4 waves per SIMD).  Rows of 65-128 words run as wave pairs
+// (k_pir_waves_pairs below), each wave with four tiles.
 // ---------------------------------------------------------------------------
-constexpr int NW3 = 8;             // waves per workgroup (two workgroups per CU at KT <= 4)
+constexpr int NW3 = 8;             // waves per workgroup
 constexpr int HMAX3 = 9;           // largest per-lane subtree height of the wave kernel
 constexpr int NT3 = 64 * NW3;
 
@@ -989,9 +990,10 @@ struct WaveTasks {
 };
 
 template <class PRF, int KT, bool VEC>
-__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 : 4))) void k_pir_waves(const WaveTasks tasks,
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_waves(const WaveTasks tasks,
                                                                                            uint32_t stride)
 {
+    static_assert(KT <= 4, "rows of 65-128 words run as wave pairs");
     __shared__ uint32_t tab[PRF::TAB_WORDS ? PRF::TAB_WORDS : 1];
     const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     const PRF P(tab, lane);
@@ -1123,6 +1125,214 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(KT > 4 ? 3 
             if (kok == 2)
                 v = 0u - v;
             atomicAdd(&out[(size_t)(grp * 16 + key) * out_step + col], v);
+        }
+    }
+}
+
+
+// ---------------------------------------------------------------------------
+// Rows of 65-128 words: wave pairs.  Eight column tiles in one wave need more
+// than 128 VGPRs, so the two waves of a pair share the work instead: both take
+// the same 16 keys, wave j of the pair walks chunk 2 c + j of the bin (its own
+// subtrees, as in k_pir_waves), and each step the two trade their leaf shares
+// through LDS; wave j then multiplies both chunks' shares into column half j
+// (columns 64 j .. 64 j + 63), four tiles of 16 columns.  Per wave that is the
+// register and table-row footprint of a 64-word row, at the cost of two LDS
+// accesses and one bounded wait per step.  Items come in pairs (2 p, 2 p + 1):
+// pair p is (key group, pair of chunks); a pair whose second chunk is past the
+// bin gives that wave no rows (zero shares).
+// ---------------------------------------------------------------------------
+constexpr uint32_t PAIR_RING = 3; // steps of shares in a wave's LDS slots
+
+template <uint32_t TABW>
+struct PairSmem {
+    uint32_t tab[TABW];                  // first: at LDS address 0
+    uint2 ring[NW3][PAIR_RING][64];       // (y0, y1) of each lane, per wave and slot
+    uint32_t wdone[NW3], rdone[NW3];      // steps written by a wave / of its partner's read by it
+};
+
+template <class PRF, bool VEC>
+__global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k_pir_waves_pairs(const WaveTasks tasks,
+                                                                                          uint32_t stride,
+                                                                                          uint32_t wait_limit)
+{
+    __shared__ PairSmem<PRF::TAB_WORDS ? PRF::TAB_WORDS : 1> sm;
+    const uint32_t tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const PRF P(sm.tab, lane);
+    if (PRF::TAB_WORDS)
+        PRF::fill(sm.tab, tid, NT3);
+    if (lane == 0) {
+        sm.wdone[wave] = 0;
+        sm.rdone[wave] = 0;
+    }
+    __syncthreads();
+
+    // pairs are whole: every task's item count is even and starts even
+    const uint32_t item0 = __builtin_amdgcn_readfirstlane(xcd_block() * NW3 + wave);
+    if (item0 >= tasks.n_items)
+        return; // the partner (item0 ^ 1) returns too; no barrier follows
+    uint32_t ti = 0;
+    while (ti + 1 < tasks.count && item0 >= tasks.t[ti + 1].item_begin)
+        ti++;
+    const WaveTask &g = tasks.t[ti];
+    const uint32_t item = item0 - g.item_begin;
+    const uint32_t j = item & 1, pw = wave ^ 1; // this wave's half; its partner
+    const uint32_t pair = item >> 1;
+    const uint32_t dim = g.dim, n_keys = g.n_keys;
+    const uint32_t pchunks = (g.chunks_per_bin + 1) / 2;
+    const uint32_t grp = pair % g.n_groups, bin_pchunk = pair / g.n_groups;
+    const uint32_t bin = bin_pchunk / pchunks, pchunk = bin_pchunk % pchunks;
+    const uint64_t first_row = (uint64_t)bin << g.n;
+    const uint64_t rows_left = g.rows - first_row;
+    const uint64_t rows = rows_left < ((uint64_t)1 << g.n) ? rows_left : ((uint64_t)1 << g.n);
+    const uint32_t *__restrict__ table = g.table + first_row * dim;
+    const uint8_t *__restrict__ keys = g.keys + (size_t)bin * stride;
+    uint32_t *__restrict__ out = g.out + (size_t)bin * dim;
+    const size_t key_step = (size_t)g.n_bins * stride, out_step = (size_t)g.n_bins * dim;
+    const uint32_t q = lane & 15, sub = lane >> 4, ncol = lane & 15;
+    const uint32_t kq = grp * 16 + q;
+    const uint32_t h = g.h;
+    if (h == 0 || h > g.n || h > HMAX3)
+        return; // the same for both waves of the pair; no barrier follows
+
+    uint32_t ok = 0;
+    const KeyView K{keys + (size_t)(kq < n_keys ? kq : 0) * key_step};
+    const CwGlobal C = cw_global(K);
+    if (kq < n_keys) {
+        const uint32_t hdr = *reinterpret_cast<const uint32_t *>(K.p);
+        const uint32_t ver = hdr & 0xff, party = (hdr >> 8) & 0xff, kn = (hdr >> 16) & 0xff, prf = hdr >> 24;
+        ok = (ver == PIR_KEY_VERSION && party <= 1 && kn == g.n && prf == PRF::id) ? 1u + party : 0u;
+        if (!ok && sub == 0 && j == 0)
+            atomicOr(tasks.status, PIR_STATUS_BAD_KEY);
+    }
+    // the two chunks of the pair; a chunk past the bin reads chunk 2 pchunk's rows
+    // (with zero shares)
+    const uint32_t c_own = 2 * pchunk + j, c_par = 2 * pchunk + (1 - j);
+    const bool own_ok = c_own < g.chunks_per_bin, par_ok = c_par < g.chunks_per_bin;
+    auto chunk_base = [&](uint32_t c, bool valid, uint32_t &last_off) {
+        const uint64_t r0 = ((uint64_t)(valid ? c : 2 * pchunk) * 4) << h;
+        const uint64_t n_r = rows - r0 < ((uint64_t)4 << h) ? rows - r0 : ((uint64_t)4 << h);
+        last_off = (uint32_t)(n_r - 1) * dim;
+        return table + r0 * dim + 64 * j; // column half j
+    };
+    uint32_t last_own, last_par;
+    const uint32_t *__restrict__ ctab_own = chunk_base(c_own, own_ok, last_own);
+    const uint32_t *__restrict__ ctab_par = chunk_base(c_par, par_ok, last_par);
+    const uint32_t hdim = dim - 64 * j < 64 ? dim - 64 * j : 64; // columns in this half (>= 1)
+    // VEC (dim a multiple of 4): lane n reads columns 4 n .. 4 n + 3 of the
+    // half with one 16-byte load; a lane past the half's end reads the last
+    // four columns instead, which only feed output columns that are never
+    // written (column n of a tile takes only table column n)
+    const uint32_t nld = VEC ? (ncol < hdim / 4 ? ncol : hdim / 4 - 1) : ncol;
+
+    const uint64_t lane_row0 = ((uint64_t)c_own * 4 + sub) << h;
+    const bool active = ok && own_ok && lane_row0 < rows;
+
+    Seed node{{0, 0, 0, 0}};
+    if (active) {
+        node = K.root();
+        for (uint32_t d = 1; d + h <= g.n; d++)
+            node = child_on_path(P, C, node, d, (uint32_t)((g.row0 + lane_row0) >> (g.n - d)) & 1u);
+    }
+    const uint32_t d0 = g.n - h;
+    Seed right[HMAX3];
+#pragma unroll
+    for (int i = 0; i < HMAX3; i++)
+        right[i] = Seed{{0, 0, 0, 0}};
+
+    v4i tot[4];
+#pragma unroll
+    for (int t = 0; t < 4; t++)
+        tot[t] = v4i{0, 0, 0, 0};
+    const uint32_t steps = 1u << (h - 1);
+    bool stalled = false;
+    // The partner's shares of step m - 1 are multiplied in at step m (and its
+    // last step's after the loop), so that a wave waits only when its partner
+    // is more than a step behind.
+    auto partner_step = [&](uint32_t m, uint32_t off) { // the partner's step m, rows at off
+        uint32_t u0[4], u1[4];
+        load_cols<4, VEC>(ctab_par + (off < last_par ? off : last_par), hdim, nld, u0);
+        load_cols<4, VEC>(ctab_par + (off + dim < last_par ? off + dim : last_par), hdim, nld, u1);
+        if (!wait_count(&sm.wdone[pw], m + 1, wait_limit))
+            return false;
+        const uint2 z = sm.ring[pw][m % PAIR_RING][lane];
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup"); // the read is done before it is reported
+        if (lane == 0)
+            __hip_atomic_store(&sm.rdone[wave], m + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        mfma_step<4>(z.x, z.y, u0, u1, tot);
+        return true;
+    };
+    uint32_t row_off = (sub << h) * dim; // this lane's row 2m in either chunk
+    for (uint32_t m = 0; m < steps; m++, row_off += 2 * dim) {
+        const uint64_t r0 = lane_row0 + 2 * m;
+        uint32_t t0[4], t1[4];
+        load_cols<4, VEC>(ctab_own + (row_off < last_own ? row_off : last_own), hdim, nld, t0);
+        load_cols<4, VEC>(ctab_own + (row_off + dim < last_own ? row_off + dim : last_own), hdim, nld, t1);
+
+        uint32_t kst = 1;
+        if (m != 0) {
+            const uint32_t kf = __builtin_amdgcn_readfirstlane(h - 1 - __builtin_ctz(m));
+#pragma unroll
+            for (int i = 1; i < HMAX3; i++)
+                if ((uint32_t)i == kf)
+                    node = right[i];
+            kst = kf + 1;
+        }
+        uint32_t y0 = 0, y1 = 0;
+        if (active) {
+            for (uint32_t k = __builtin_amdgcn_readfirstlane(kst); k < h; k++) {
+                Seed c0, c1;
+                children(P, C, node, d0 + k, c0, c1);
+#pragma unroll
+                for (int i = 1; i < HMAX3; i++)
+                    if ((uint32_t)i == k)
+                        right[i] = c1;
+                node = c0;
+            }
+            const uint2 cw = C.cw_word0(g.n, node.w[0] & 1u);
+            P.pair_word0(node.w, y0, y1);
+            y0 = r0 < rows ? y0 ^ cw.x : 0u;
+            y1 = r0 + 1 < rows ? y1 ^ cw.y : 0u;
+        }
+
+        // hand this step's shares to the partner: slot m mod PAIR_RING is free
+        // once the partner has read step m - PAIR_RING from it
+        if (m >= PAIR_RING && !wait_count(&sm.rdone[pw], m - PAIR_RING + 1, wait_limit)) {
+            stalled = true;
+            break;
+        }
+        sm.ring[wave][m % PAIR_RING][lane] = make_uint2(y0, y1);
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        if (lane == 0)
+            __hip_atomic_store(&sm.wdone[wave], m + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+
+        mfma_step<4>(y0, y1, t0, t1, tot); // own rows, column half j
+        if (m != 0 && !partner_step(m - 1, row_off - 2 * dim)) {
+            stalled = true;
+            break;
+        }
+    }
+    if (!stalled && !partner_step(steps - 1, row_off - 2 * dim))
+        stalled = true;
+    if (stalled && lane == 0)
+        atomicOr(tasks.status, PIR_STATUS_STALLED);
+
+    // lane l holds D[(l / 16) * 4 + i][l mod 16] of every tile, column half j
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t key = (lane >> 4) * 4 + i;
+        const uint32_t kok = __shfl(ok, (int)key);
+        if (!kok)
+            continue;
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+            const uint32_t col = col_of<4, VEC>(ncol, t);
+            if (col >= hdim)
+                continue;
+            uint32_t v = (uint32_t)tot[t][i];
+            if (kok == 2)
+                v = 0u - v;
+            atomicAdd(&out[(size_t)(grp * 16 + key) * out_step + 64 * j + col], v);
         }
     }
 }

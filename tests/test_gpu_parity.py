@@ -541,8 +541,9 @@ def test_single_key_streamed_wide_rows(O, pirmod, prf, dim):
 
 
 WIDE_WAVE_CASES = [
-    # rows, dim, keys: rows of 65..128 words on the wave kernel (eight column
-    # tiles), several key groups, ragged row counts and key groups
+    # rows, dim, keys: rows of 65..128 words on the wave kernel (wave pairs,
+    # four column tiles a wave), several key groups, ragged row counts and
+    # key groups
     ((1 << 16) + 3, 65, 41), ((1 << 17) - 1, 100, 25), ((1 << 17) + 5, 128, 48), ((1 << 16) + 9, 127, 32),
     ((1 << 14) - 3, 100, 528),
 ]
@@ -551,9 +552,10 @@ WIDE_WAVE_CASES = [
 @pytest.mark.parametrize("prf", [0, 1])
 @pytest.mark.parametrize("rows,dim,nkeys", WIDE_WAVE_CASES)
 def test_wide_rows_wave_kernel(O, pirmod, prf, rows, dim, nkeys):
-    """Batches on rows of 65 to 128 words, which the wave kernel takes with
-    eight column tiles per lane: every per-server answer against the oracle
-    and every reconstruction against T[alpha]."""
+    """Batches on rows of 65 to 128 words, which the wave kernel takes as wave
+    pairs (each wave one 64-column half of both chunks' rows): every
+    per-server answer against the oracle and every reconstruction against
+    T[alpha]."""
     import torch
 
     assert pirmod.plan(nkeys, rows, dim, prf=prf)["kernel"] == pirmod.KERNEL_WAVES
@@ -573,6 +575,51 @@ def test_wide_rows_wave_kernel(O, pirmod, prf, rows, dim, nkeys):
     for i, a in enumerate(alphas):
         assert (O.reconstruct(got[i], got[nkeys + i]) == Tn[a]).all(), i
 
+
+
+@pytest.mark.parametrize("prf", [0, 1])
+def test_wave_pairs_several_tables_one_launch(O, pirmod, prf):
+    """Rows of 65..128 words run as wave pairs: two waves on the same 16 keys
+    and adjacent chunks trade their leaf shares, and each multiplies one
+    64-column half.  Six such tables in one call share the launches of their
+    column classes (every table's pairs start at an even item); odd chunk
+    counts leave the last pair's second wave without rows; the second half
+    is full, partial with a width that is a multiple of 4 (16-byte loads
+    kept inside the row), or of any width (single words); and one table sits
+    at a 4-byte offset.  Every per-server answer against the oracle."""
+    import torch
+
+    specs = [  # rows, dim, keys, at a 4-byte offset; chunks of 2048 rows
+        (9000, 128, 33, False),  # 5 chunks
+        (3000, 100, 21, False),  # 2 chunks, second half of 36 columns
+        (7000, 68, 40, False),   # 4 chunks, second half of 4 columns
+        (5000, 99, 17, False),   # 3 chunks, single words
+        (4100, 128, 18, True),   # 3 chunks, single words (unaligned)
+        (4100, 128, 18, False),  # the same rows and keys, aligned
+    ]
+    tables, counts, keysets, expect = [], [], [], []
+    for t, (rows, dim, nk, offset) in enumerate(specs):
+        seed = 900 + (t if t < 5 else 4) + prf
+        T = W.make_table(rows, dim, seed)
+        if offset:
+            buf = torch.empty(rows * dim + 4, dtype=torch.int32, device="cuda")
+            Td = buf[1:1 + rows * dim].view(rows, dim)
+            Td.copy_(T.cuda())
+            assert Td.data_ptr() % 16 != 0
+        else:
+            Td = T.cuda()
+        tables.append(Td)
+        counts.append(nk)
+        K, _ = O.gen_batch(log_domain(rows), W.uniform_indices(rows, nk, seed), W.key_seeds(nk, seed), prf_id=prf)
+        keysets.append(K)
+        expect.append(O.answer_batch(K, T.numpy().view(np.uint32), nthreads=cpu_threads()))
+    stride = (max(k.shape[1] for k in keysets) + 15) // 16 * 16
+    keys = np.concatenate([np.pad(k, ((0, 0), (0, stride - k.shape[1]))) for k in keysets])
+    _, views = pirmod.answer_multi(tables, counts, torch.from_numpy(keys).cuda(), prf=prf)
+    torch.cuda.synchronize()
+    for t, (v, e) in enumerate(zip(views, expect)):
+        assert (v.cpu().numpy().view(np.uint32) == e).all(), specs[t]
+    assert (views[4].cpu() == views[5].cpu()).all()
 
 @pytest.mark.parametrize("prf", [0, 1])
 def test_full_size_2p20_x128_batch64(O, pirmod, prf):

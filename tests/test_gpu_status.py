@@ -319,3 +319,34 @@ def test_a_stalled_wait_is_reported_and_the_kernel_ends(O, pirmod):
     assert pirmod.check_status() == pirmod.PIR_OK
     rec = pirmod.reconstruct(o0.cpu().numpy().view(np.uint32)[0], o1.cpu().numpy().view(np.uint32)[0])
     assert (rec == W.table_rows_np(a, dim, 41)[0]).all()
+
+
+
+def test_a_stalled_pair_wait_ends_the_kernel(O, pirmod):
+    """The wave pairs' bounded waits (rows of 65..128 words) with a wait limit
+    of one try: the kernel ends whatever its waits see, and the call reports
+    PIR_ESTALL, or PIR_OK with exact answers if no wait had to give up; with
+    the default limit restored the same keys answer exactly and report PIR_OK."""
+    import torch
+
+    rows, dim, nk = 1 << 18, 128, 64
+    assert pirmod.plan(nk, rows, dim)["kernel"] == pirmod.KERNEL_WAVES
+    T = W.make_table(rows, dim, 43)
+    Td = T.cuda()
+    K = keyset(O, rows, nk, 43)
+    want = O.answer_batch(K, T.numpy().view(np.uint32), nthreads=cpu_threads())
+    keys = torch.from_numpy(K).cuda()
+    try:
+        pirmod.set_wait_limit(1)
+        out = pirmod.answer(keys, Td)
+        torch.cuda.synchronize()
+        st = pirmod.check_status()
+        assert st in (pirmod.PIR_ESTALL, pirmod.PIR_OK)
+        if st == pirmod.PIR_OK:
+            assert (out.cpu().numpy().view(np.uint32) == want).all()
+    finally:
+        pirmod.set_wait_limit(0)
+    out = pirmod.answer(keys, Td)
+    torch.cuda.synchronize()
+    assert pirmod.check_status() == pirmod.PIR_OK
+    assert (out.cpu().numpy().view(np.uint32) == want).all()
