@@ -69,8 +69,8 @@ KERNEL_SOURCES = ["paper_2301_10904_amd/csrc/pir_kernels.h", "paper_2301_10904_a
 TRAFFIC_SUMMARY = {
     ("aes128", 20, 1024, 64): ROOT / "profiles" / "k_pir_waves_2p20x64_b1024_traffic.json",
     ("chacha20", 20, 1024, 64): ROOT / "profiles" / "k_pir_waves_chacha20_2p20x64_b1024_traffic.json",
-    ("aes128", 20, 1024, 128): ROOT / "profiles" / "k_pir_waves_2p20x128_b1024_traffic.json",
-    ("chacha20", 20, 1024, 128): ROOT / "profiles" / "k_pir_waves_chacha20_2p20x128_b1024_traffic.json",
+    ("aes128", 20, 1024, 128): ROOT / "profiles" / "k_pir_waves_pairs_2p20x128_b1024_traffic.json",
+    ("chacha20", 20, 1024, 128): ROOT / "profiles" / "k_pir_waves_pairs_chacha20_2p20x128_b1024_traffic.json",
 }
 
 

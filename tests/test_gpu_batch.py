@@ -54,7 +54,7 @@ CASES = [
     # rows, dim, bin_log, clients: one group, partial groups, several groups, ragged last bin
     (1 << 12, 16, 8, 1), (1 << 12, 64, 10, 5), (3000, 7, 6, 17), (5000, 32, 9, 40),
     (1 << 14, 64, 12, 16), (777, 3, 3, 2), (1 << 13, 33, 13, 20),
-    # rows of 65..128 words (eight column tiles per lane)
+    # rows of 65..128 words (wave pairs, four column tiles a wave)
     (1 << 12, 128, 9, 6), (3000, 100, 7, 17), (2000, 65, 11, 3),
     # tables of 1..4 rows: a single bin shorter than any wave item's subtrees
     (1, 16, 3, 3), (2, 64, 3, 2), (3, 5, 4, 17), (4, 128, 3, 1), (4, 32, 12, 16),

@@ -810,7 +810,7 @@ def test_random_shapes_against_the_oracle(O, pirmod):
     (1 << 12, 16, 64),    # wave kernel, 16 columns
     (1 << 14, 64, 3),     # small-batch kernel (16-byte row segments when aligned)
     (1 << 14, 64, 16),    # small-batch kernel, matrix-core product over 16 keys
-    (1 << 12, 100, 40),   # eight column tiles
+    (1 << 12, 100, 40),   # wave pairs: single words here, 16-byte loads on the aligned copy
 ])
 def test_table_at_a_4_byte_offset(O, pirmod, prf, rows, dim, nkeys):
     """A table whose base is 4-byte but not 16-byte aligned (a contiguous view
