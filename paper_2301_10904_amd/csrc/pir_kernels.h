@@ -965,6 +965,45 @@ __global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4))) void k_
 // 4 waves per SIMD).  Rows of 65-128 words run as wave pairs
 // (k_pir_waves_pairs below), each wave with four tiles.
 // ---------------------------------------------------------------------------
+// Adds a wave's answer tiles into out: tile t of lane l holds
+// D[(l / 16) 4 + i][l mod 16], the total of key key0 + (l / 16) 4 + i at column
+// col0 + col_of<KT, PACKED>(l mod 16, t); ok is the lane's key status (0 =
+// skip, 1 or 2 = party 0 or 1, which negates).  Packed columns (lane n holds
+// columns n KT .. n KT + KT - 1) are first regrouped across the 16 lanes of a
+// key row, so that each atomic instruction adds 16 consecutive columns of four
+// keys: 64 bytes a key instead of words 4 KT bytes apart, a quarter of the
+// memory footprint at KT = 4.
+template <int KT, bool PACKED>
+__device__ __forceinline__ void add_tiles(const v4i (&tot)[KT], uint32_t ok, uint32_t lane, uint32_t ncols,
+                                          uint32_t *__restrict__ out, size_t out_step, uint32_t key0, uint32_t col0)
+{
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        const uint32_t key = (lane >> 4) * 4 + i;
+        const uint32_t kok = __shfl(ok, (int)key);
+#pragma unroll
+        for (int t = 0; t < KT; t++) {
+            uint32_t col, v;
+            if constexpr (PACKED && KT > 1) {
+                // column 16 t + n of the row is tile (16 t + n) mod KT of lane (16 t + n) / KT
+                col = 16 * (uint32_t)t + (lane & 15);
+                const uint32_t src = (lane & 48) | (col / KT), ts = col % KT;
+                v = 0;
+#pragma unroll
+                for (int u = 0; u < KT; u++) {
+                    const uint32_t x = (uint32_t)__shfl(tot[u][i], (int)src); // every lane takes part
+                    v = (uint32_t)u == ts ? x : v;
+                }
+            } else {
+                col = col_of<KT, PACKED>(lane & 15, t);
+                v = (uint32_t)tot[t][i];
+            }
+            if (kok && col < ncols)
+                atomicAdd(&out[(size_t)(key0 + key) * out_step + col0 + col], kok == 2 ? 0u - v : v);
+        }
+    }
+}
+
 constexpr int NW3 = 8;             // waves per workgroup
 constexpr int HMAX3 = 9;           // largest per-lane subtree height of the wave kernel
 constexpr int NT3 = 64 * NW3;
@@ -1109,24 +1148,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
         mfma_step<KT>(y0, y1, t0, t1, tot);
     }
 
-    // lane l holds D[(l / 16) * 4 + i][l mod 16] of every (shift, tile)
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const uint32_t key = (lane >> 4) * 4 + i;
-        const uint32_t kok = __shfl(ok, (int)key);
-        if (!kok)
-            continue;
-#pragma unroll
-        for (int t = 0; t < KT; t++) {
-            const uint32_t col = col_of<KT, VEC>(ncol, t);
-            if (col >= dim)
-                continue;
-            uint32_t v = (uint32_t)tot[t][i];
-            if (kok == 2)
-                v = 0u - v;
-            atomicAdd(&out[(size_t)(grp * 16 + key) * out_step + col], v);
-        }
-    }
+    add_tiles<KT, VEC>(tot, ok, lane, dim, out, out_step, grp * 16, 0);
 }
 
 
@@ -1317,24 +1339,7 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
     if (stalled && lane == 0)
         atomicOr(tasks.status, PIR_STATUS_STALLED);
 
-    // lane l holds D[(l / 16) * 4 + i][l mod 16] of every tile, column half j
-#pragma unroll
-    for (int i = 0; i < 4; i++) {
-        const uint32_t key = (lane >> 4) * 4 + i;
-        const uint32_t kok = __shfl(ok, (int)key);
-        if (!kok)
-            continue;
-#pragma unroll
-        for (int t = 0; t < 4; t++) {
-            const uint32_t col = col_of<4, VEC>(ncol, t);
-            if (col >= hdim)
-                continue;
-            uint32_t v = (uint32_t)tot[t][i];
-            if (kok == 2)
-                v = 0u - v;
-            atomicAdd(&out[(size_t)(grp * 16 + key) * out_step + 64 * j + col], v);
-        }
-    }
+    add_tiles<4, VEC>(tot, ok, lane, hdim, out, out_step, grp * 16, 64 * j); // column half j
 }
 
 } // namespace
