@@ -1158,13 +1158,15 @@ __global__ __launch_bounds__(NT3) __attribute__((amdgpu_waves_per_eu(4))) void k
 // the same 16 keys, wave j of the pair walks chunk 2 c + j of the bin (its own
 // subtrees, as in k_pir_waves), and each step the two trade their leaf shares
 // through LDS; wave j then multiplies both chunks' shares into column half j
-// (columns 64 j .. 64 j + 63), four tiles of 16 columns.  Per wave that is the
-// register and table-row footprint of a 64-word row, at the cost of two LDS
-// accesses and one bounded wait per step.  Items come in pairs (2 p, 2 p + 1):
-// pair p is (key group, pair of chunks); a pair whose second chunk is past the
-// bin gives that wave no rows (zero shares).
+// (columns 64 j .. 64 j + 63), four tiles of 16 columns: its own shares of
+// the step, and its partner's of the step before, so that a wave can run a
+// step ahead of its partner before it waits.  Per wave that is the register
+// and table-row footprint of a 64-word row (4 waves per SIMD), at the cost of
+// two LDS accesses and two bounded waits per step.  Items come in pairs
+// (2 p, 2 p + 1): pair p is (key group, pair of chunks); a pair whose second
+// chunk is past the bin gives that wave no rows (zero shares).
 // ---------------------------------------------------------------------------
-constexpr uint32_t PAIR_RING = 3; // steps of shares in a wave's LDS slots
+constexpr uint32_t PAIR_RING = 3; // steps of shares in a wave's LDS slots (two workgroups per CU)
 
 template <uint32_t TABW>
 struct PairSmem {
