@@ -55,6 +55,27 @@ def test_tree_kernels_keep_their_lds_tables(device_asm):
         assert scratch <= 64, f"{name}: {scratch} bytes of scratch per lane"
 
 
+
+def test_plans_report_the_wave_kernels_lds(device_asm):
+    """pir_plan's lds_bytes for the wave kernel is the static LDS the assembled
+    kernel allocates: the AES tables for rows of up to 64 words, and for the
+    wave pairs of 65..128-word rows the tables plus the share ring."""
+    from paper_2301_10904_amd import pir
+
+    meta = kernel_metadata(device_asm)
+
+    def lds_of(sub):
+        found = {lds for name, (lds, _) in meta.items() if sub in name}
+        assert len(found) == 1, (sub, found)
+        return found.pop()
+
+    pairs_aes = lds_of("k_pir_waves_pairsINS_6AesPrf")
+    pairs_chacha = lds_of("k_pir_waves_pairsINS_9ChaChaPrf")
+    assert pir.plan(1024, 1 << 20, 128)["lds_bytes"] == pairs_aes
+    assert pir.plan(1024, 1 << 20, 100, prf="chacha20")["lds_bytes"] == pairs_chacha
+    assert pir.plan_bins(1 << 20, 128, 64, 12)["lds_bytes"] == pairs_aes
+    assert pir.plan(1024, 1 << 20, 64)["lds_bytes"] == lds_of("k_pir_wavesINS_6AesPrfELi4ELb1")
+
 def test_bitsliced_prf_engine_builds_without_scratch():
     """The bitsliced AES-128 engine (measurement library) compiles, which runs
     its compile-time checks of the tower-field S-box circuit against the

@@ -518,6 +518,28 @@ def test_workspace_binding_is_per_thread(lib):
     assert all(r == (pir.PIR_OK, pir.PIR_EINVAL, pir.PIR_OK) for r in res.values())
 
 
+def test_plan_wave_pairs_count_items_in_pairs():
+    """Rows of 65..128 words run as wave pairs: two waves on adjacent chunks of
+    a bin share a key group, so a plan counts a bin's chunks rounded up to an
+    even number, and every launch's item count is even (both waves of a pair
+    exist and leave together)."""
+    for prf in ("aes128", "chacha20"):
+        for rows in (9000, 5 * 2048 + 7, 1 << 20, (1 << 20) + 5):
+            for dim in (65, 100, 128):
+                for keys in (64, 1024):
+                    p = pir.plan(keys, rows, dim, prf=prf)
+                    if p["kernel"] != pir.KERNEL_WAVES:
+                        continue
+                    chunks = -(-rows // p["rows_per_item"])
+                    assert p["items"] % 2 == 0
+                    assert p["items"] == 2 * -(-chunks // 2) * -(-(keys - p["tail_keys"]) // 16), (rows, dim, keys, p)
+        for rows, bin_log, clients in ((3000, 10, 17), (1 << 14, 12, 5), (5 * 2048 + 7, 13, 40)):
+            p = pir.plan_bins(rows, 100, clients, bin_log, prf=prf)
+            bin_rows = min(rows, 1 << bin_log)
+            chunks = -(-bin_rows // p["rows_per_item"])
+            assert p["items"] == pir.n_bins(rows, bin_log) * 2 * -(-chunks // 2) * -(-clients // 16), p
+
+
 @pytest.mark.parametrize("rows", [1, 2, 3, 4, 5, 8, 9, 777, 1 << 14])
 @pytest.mark.parametrize("bin_log", [3, 4, 10, 32])
 def test_plan_bins_subtree_height_stays_in_the_bin(rows, bin_log):
