@@ -291,6 +291,9 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, int c
         return PIR_OK;
     const dim3 grid((uint32_t)((items + NW3 - 1) / NW3));
 #define PIR_LAUNCH_WAVES(KT, VEC) hipLaunchKernelGGL((k_pir_waves<PRF, KT, VEC>), grid, dim3(NT3), 0, st, W, key_stride)
+#define PIR_LAUNCH_PAIRS(VEC)                                                                                      \
+    hipLaunchKernelGGL((k_pir_waves_pairs<PRF, VEC>), grid, dim3(NT3), 0, st, W, key_stride,                        \
+                       g_wait_limit.load(std::memory_order_relaxed))
     switch (cls) {
     case 0: PIR_LAUNCH_WAVES(4, true); break;
     case 1: PIR_LAUNCH_WAVES(2, true); break;
@@ -298,9 +301,6 @@ static int launch_waves(WaveTask *ts, uint32_t count, uint32_t key_stride, int c
     case 3: PIR_LAUNCH_WAVES(1, false); break;
     case 4: PIR_LAUNCH_WAVES(2, false); break;
     case 5: PIR_LAUNCH_WAVES(4, false); break;
-#define PIR_LAUNCH_PAIRS(VEC)                                                                                      \
-    hipLaunchKernelGGL((k_pir_waves_pairs<PRF, VEC>), grid, dim3(NT3), 0, st, W, key_stride,                        \
-                       g_wait_limit.load(std::memory_order_relaxed))
     case 6: PIR_LAUNCH_PAIRS(false); break;
     case 7: PIR_LAUNCH_PAIRS(true); break;
     default: return PIR_EINVAL;
