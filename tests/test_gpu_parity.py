@@ -463,6 +463,7 @@ SLICE_CASES = [
     (12, 4, 16, 3), (14, 8, 64, 40), (16, 2, 7, 20), (13, 16, 33, 1), (10, 64, 4, 17), (15, 4, 130, 5),
     (14, 4, 100, 20),
     (18, 2, 16, 36),  # slices of 2^17 rows: a remainder of 4 keys runs as a launch of its own
+    (18, 2, 100, 24),  # slices of 2^17 rows of 100 words on the wave pairs
 ]
 
 
